@@ -1,0 +1,442 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms,
+brute force on tiny inputs, an independent quadrature of a defining integral,
+invariants, or a hand-worked fixture.
+"""
+import json
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import synth
+from oracle import fdas64 as o
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- spectrum
+
+def test_spectrum_brute_force_dft_tiny():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(64).astype(np.float32)
+    n = len(x)
+    want = np.array([sum(float(x[t]) * np.exp(-2j * np.pi * r * t / n) for t in range(n))
+                     for r in range(n // 2)])
+    want[0] = 0
+    np.testing.assert_allclose(o.spectrum(x), want, rtol=0, atol=1e-12)
+
+
+def test_spectrum_parseval():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(1 << 14)
+    a = o.spectrum(x)
+    n = len(x)
+    dc = math.fsum(x)                                    # X_0 by direct sum
+    nyq = math.fsum(x * (-1.0) ** np.arange(n))          # X_{N/2} by direct sum
+    lhs = math.fsum(x * x)
+    rhs = (dc * dc + 2.0 * math.fsum(np.abs(a[1:]) ** 2) + nyq * nyq) / n
+    assert abs(lhs - rhs) <= 1e-12 * lhs
+
+
+def test_spectrum_integer_bin_sinusoid_closed_form():
+    n, a, r, ph = 1 << 17, 0.05, 5000, 0.7
+    x = a * np.cos(2 * np.pi * r * np.arange(n) / n + ph)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    p = np.abs(s) ** 2
+    assert abs(p[r] - n * a * a / 4) < 1e-9 * (n * a * a / 4)   # 81.92
+    assert abs(p[r] - 81.92) < 1e-9
+    assert abs(np.angle(s[r]) - ph) < 1e-9
+    p[r] = 0
+    assert p.max() < 1e-18
+
+
+# ----------------------------------------------------------- normalisation
+
+def test_median_normalisation_constructed_blocks():
+    b = 2048
+    rng = np.random.default_rng(2)
+    blocks = []
+    for i in range(4):
+        vals = rng.permutation(np.arange(1, b + 1, dtype=np.float64)) * (i + 1)
+        ph = rng.uniform(0, 2 * np.pi, b)
+        blocks.append(np.sqrt(vals) * np.exp(1j * ph))
+    a = np.concatenate(blocks)
+    out, med = o.normalise(a, "median", block=b, return_medians=True)
+    # lower median of {1..2048} * (i+1) is 1024 * (i+1)
+    np.testing.assert_allclose(med, [1024.0 * (i + 1) for i in range(4)], rtol=1e-15)
+    for i in range(4):
+        seg = out[i * b:(i + 1) * b]
+        np.testing.assert_allclose(seg, a[i * b:(i + 1) * b] * math.sqrt(math.log(2) / (1024.0 * (i + 1))),
+                                   rtol=1e-15)
+        # the median power of every block becomes ln 2 exactly (up to rounding)
+        assert abs(np.sort(np.abs(seg) ** 2)[(b - 1) // 2] - math.log(2)) < 1e-14
+
+
+def test_median_normalisation_noise_unit_mean():
+    x = synth.make_series(1 << 20, [], cfg_seed=9, series_index=0)
+    a = o.normalise(o.spectrum(x), "median")
+    p = np.abs(a[1:]) ** 2
+    assert abs(p.mean() - 1.0) < 0.01
+    v = o.normalise(o.spectrum(x), "variance", n_samples=len(x))
+    assert abs(np.mean(np.abs(v[1:]) ** 2) - 1.0) < 0.01
+
+
+def test_zero_median_block_scales_to_zero():
+    a = np.zeros(4096, complex)
+    a[5] = 3.0
+    out = o.normalise(a, "median")
+    assert np.all(out == 0)
+
+
+# ------------------------------------------------------- Fresnel response
+
+RESP_POINTS = [(0.0, 20.0), (3.0, 20.0), (-7.0, 20.0), (0.37, 5.5), (12.0, -33.0), (-64.0, 96.0),
+               (64.0, -96.0), (1.5, 0.02), (-2.25, -1.0), (40.0, 0.5), (0.0, 96.0), (10.0, 3e-3)]
+
+
+def _mp_rho(q, z):
+    f = lambda u: mpmath.expj(-2 * mpmath.pi * q * u + mpmath.pi * z * (u - 0.5) ** 2)
+    pts = mpmath.linspace(0, 1, 2 + int(abs(q) + abs(z)))
+    return complex(mpmath.quad(f, pts))
+
+
+@pytest.mark.parametrize("q,z", RESP_POINTS)
+def test_response_matches_mpmath_quadrature(q, z):
+    mpmath.mp.dps = 30
+    assert abs(complex(o.response(q, z)) - _mp_rho(q, z)) < 1e-12
+
+
+def test_response_matches_fine_simpson_grid():
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-70, 70, 200)
+    z = rng.uniform(-100, 100, 200)
+    u = np.linspace(0, 1, 200001)
+    w = np.ones_like(u)
+    w[1:-1:2], w[2:-1:2] = 4, 2
+    w /= 3 * (len(u) - 1)
+    f = np.exp(1j * (-2 * np.pi * q[:, None] * u + np.pi * z[:, None] * (u - 0.5) ** 2))
+    np.testing.assert_allclose(o.response(q, z), f @ w, rtol=0, atol=1e-9)
+
+
+def test_response_integer_q_at_zero_drift_is_delta():
+    q = np.arange(-20, 21, dtype=float)
+    r = o.response(q, 0.0)
+    want = (q == 0).astype(float)
+    np.testing.assert_allclose(r, want, atol=1e-13)
+
+
+def test_response_parseval_over_all_q():
+    # sum over integer q of |rho(q,z)|^2 = int_0^1 |e^{i phi}|^2 du = 1
+    q = np.arange(-20000, 20001, dtype=float)
+    for z in (5.0, 37.0, -96.0):
+        s = np.sum(np.abs(o.response(q, z)) ** 2)
+        assert abs(s - 1.0) < 5e-5
+
+
+def test_response_symmetries():
+    rng = np.random.default_rng(4)
+    q = rng.uniform(-50, 50, 50)
+    z = rng.uniform(1, 90, 50)
+    R = lambda q, z: np.exp(1j * np.pi * q) * o.response(q, z)
+    np.testing.assert_allclose(R(q, z), R(-q, z), atol=1e-12)           # even in q
+    np.testing.assert_allclose(R(q, -z), np.conj(R(q, z)), atol=1e-12)  # conjugate under z -> -z
+
+
+@pytest.mark.parametrize("z", [20.0, -35.0])
+def test_chirp_spectrum_follows_response(z):
+    """DFT of a synthesised chirp: A_{rbar+q} = (N a/2) e^{i theta} rho(q, z)."""
+    n, a = 1 << 17, 0.05
+    r0 = 5000.0 - z / 2          # mean frequency rbar = 5000 exactly
+    inj = synth.Injection(a, r0, z, 0.3)
+    x = synth.chirp(n, inj)
+    A = o.spectrum(x)
+    rbar = 5000
+    q = np.arange(-30, 31)
+    ratio = A[rbar + q] / (n * a / 2 * o.response(q.astype(float), z))
+    assert np.max(np.abs(np.abs(ratio) - 1)) < 1e-4
+    ph = np.angle(ratio / ratio[30])
+    assert np.max(np.abs(ph)) < 1e-4
+
+
+def test_response_derivatives_match_finite_differences_and_mpmath():
+    mpmath.mp.dps = 30
+    for q, z in [(0.3, 17.0), (-12.7, -44.0), (5.5, 0.004), (30.0, 90.0)]:
+        rho, dq, dz = o.response_derivatives(q, z)
+        e = 1e-5
+        fq = (o.response(q + e, z) - o.response(q - e, z)) / (2 * e)
+        fz = (o.response(q, z + e) - o.response(q, z - e)) / (2 * e)
+        assert abs(complex(dq) - complex(fq)) < 1e-7 * max(1, abs(complex(dq)))
+        assert abs(complex(dz) - complex(fz)) < 1e-7 * max(1, abs(complex(dz)))
+        g = lambda u: (-2j * mpmath.pi * u) * mpmath.expj(-2 * mpmath.pi * q * u + mpmath.pi * z * (u - 0.5) ** 2)
+        h = lambda u: (1j * mpmath.pi * (u - 0.5) ** 2) * mpmath.expj(-2 * mpmath.pi * q * u + mpmath.pi * z * (u - 0.5) ** 2)
+        pts = mpmath.linspace(0, 1, 2 + int(abs(q) + abs(z)))
+        assert abs(complex(dq) - complex(mpmath.quad(g, pts))) < 1e-11
+        assert abs(complex(dz) - complex(mpmath.quad(h, pts))) < 1e-11
+
+
+# -------------------------------------------------------------- templates
+
+def test_template_zero_drift_is_delta_and_unit_energy():
+    zs = o.z_grid(-16, 16, 2)
+    taps, hmax = o.template_taps(zs)
+    assert hmax == 24
+    j0 = int(np.argmin(np.abs(zs)))
+    want = np.zeros(2 * hmax + 1)
+    want[hmax] = 1
+    np.testing.assert_allclose(taps[j0], want, atol=1e-13)
+    np.testing.assert_allclose(np.sum(np.abs(taps) ** 2, axis=1), 1.0, rtol=1e-13)
+    # support is |q| <= ceil(|z|/2) + 16
+    for z, row in zip(zs, taps):
+        h = int(math.ceil(abs(z) / 2)) + 16
+        q = np.arange(-hmax, hmax + 1)
+        assert np.all(row[np.abs(q) > h] == 0)
+        assert np.all(np.abs(row[np.abs(q) <= h]) > 0) or z == 0
+
+
+def test_ska_grid_has_193_trials():
+    g = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))
+    zs = o.z_grid(-96, 96, 1)
+    assert len(zs) == g["ska_like"]["acceleration_trials"]
+    assert int(o.half_width(zs).max()) == 64
+
+
+# ------------------------------------------------------------ correlation
+
+def test_fft_correlation_matches_direct_sum():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(3000) + 1j * rng.standard_normal(3000)
+    taps = rng.standard_normal(41) + 1j * rng.standard_normal(41)
+    y = o.correlate(a, taps)
+    r = np.arange(3000)
+    np.testing.assert_allclose(y, o.correlate_direct(a, taps, r), atol=1e-11)
+    # and the direct sum itself against a plain loop at a few bins (edges zero-padded)
+    for rr in (0, 7, 1500, 2999):
+        s = sum(a[rr + q] * taps[q + 20] for q in range(-20, 21) if 0 <= rr + q < 3000)
+        assert abs(y[rr] - s) < 1e-11
+
+
+def test_correlation_equals_time_domain_dechirp():
+    """With the discrete, untruncated template c_q = DFT_N(g)/N of the chirp
+    g_n = exp(i pi z (n/N - 1/2)^2), correlating the full spectrum with conj(c)
+    equals the DFT of the dechirped series x * conj(g)."""
+    n, z = 4096, 7.3
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    t = np.arange(n) / n
+    g = np.exp(1j * np.pi * z * (t - 0.5) ** 2)
+    X = np.fft.fft(x)
+    c = np.fft.fft(g) / n
+    y = o.correlate_cyclic(X, np.conj(c))
+    np.testing.assert_allclose(y, np.fft.fft(x * np.conj(g)), atol=1e-9 * n)
+    # non-cyclic form on a band-limited spectrum, taps |q| <= n/4, output bin n/2
+    Xb = np.zeros(n, complex)
+    Xb[n // 4: 3 * n // 4] = X[n // 4: 3 * n // 4]
+    xb = np.fft.ifft(Xb)
+    q = np.arange(-n // 4, n // 4 + 1)
+    taps = np.conj(c[q % n])
+    yb = o.correlate_direct(Xb, taps, np.array([n // 2]))[0]
+    assert abs(yb - np.fft.fft(xb * np.conj(g))[n // 2]) < 1e-9 * n
+    # and the continuous response approximates the discrete template
+    assert np.max(np.abs(o.response(q.astype(float), z) - c[q % n])) < 5e-3
+
+
+def test_injected_chirp_recovered_with_fresnel_energy():
+    """Noise-free accelerated sinusoid: the plane peaks at (rbar, z) with
+    P = (N a^2/4) E(z)."""
+    n, a = 1 << 17, 0.05
+    for z, r0 in ((20.0, 5000.0), (-20.0, 5020.0)):
+        x = synth.chirp(n, synth.Injection(a, r0, z, 1.1))
+        s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+        zs = o.z_grid(-24, 24, 2)
+        P = o.power_plane(s, zs)
+        j, r = np.unravel_index(np.argmax(P), P.shape)
+        assert zs[j] == z and r == int(r0 + z / 2)
+        want = n * a * a / 4 * o.template_energy(np.array([z]))[0]
+        assert abs(P[j, r] - want) < 2e-3 * want
+
+
+def test_small_case_edge_detection_and_scalloping_closed_forms():
+    n, a = 1 << 17, 0.05
+    x = synth.chirp(n, synth.Injection(a, 5000.0, 20.0, 0.2))
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    zs = o.z_grid(-16, 16, 2)
+    P = o.power_plane(s, zs)
+    j, r = np.unravel_index(np.argmax(P), P.shape)
+    assert (zs[j], r) == (16.0, 5010)
+    # z mismatch dz = 4: |int_{-1/2}^{1/2} e^{i pi dz v^2} dv|^2 = (2/dz)(C^2+S^2)(sqrt(dz/2))
+    S, C = sps.fresnel(math.sqrt(2.0))
+    mism = (2 / 4.0) * (C * C + S * S)
+    assert abs(P[j, r] - 81.92 * mism) < 0.01 * 81.92 * mism
+    # half-bin scalloping at z = 0: |A|^2 = 81.92 * (2/pi)^2 (to O(1/N))
+    xh = a * np.cos(2 * np.pi * 5000.5 * np.arange(n) / n)
+    sh = o.normalise(o.spectrum(xh), "variance", n_samples=n)
+    assert abs(np.max(np.abs(sh) ** 2) - 81.92 * 4 / np.pi ** 2) < 2e-4 * 33.2
+    # exact: DFT of a sampled cosine is a sum of two Dirichlet kernels
+    D = lambda d: np.exp(-1j * np.pi * d * (n - 1) / n) * np.sin(np.pi * d) / np.sin(np.pi * d / n)
+    k = 5000
+    want = (a / 2) * (D(k - 5000.5) + D(k + 5000.5)) / math.sqrt(n)
+    assert abs(sh[k] - want) < 1e-10
+
+
+def test_noise_rows_have_unit_mean_power():
+    x = synth.make_series(1 << 18, [], 11, 0)
+    s = o.normalise(o.spectrum(x), "median")
+    zs = np.array([-96.0, -41.0, 0.0, 17.0, 96.0])
+    P = o.power_plane(s, zs)
+    m = P[:, 200:-200].mean(axis=1)
+    assert np.all(np.abs(m - 1) < 0.02)
+    # exponential marginal: P(P > 3) = e^-3
+    frac = (P[:, 200:-200] > 3).mean(axis=1)
+    assert np.all(np.abs(frac - math.exp(-3)) < 0.005)
+
+
+# ---------------------------------------------------------- harmonic sums
+
+def _plane_from_formula(nz, nb):
+    j = np.arange(nz)[:, None]
+    r = np.arange(nb)[None, :]
+    return (100 * j + r).astype(float)
+
+
+def test_harmonic_sum_worked_fixture():
+    g = json.load(open(os.path.join(GOLDEN, "harmonic_sum_worked.json")))
+    P = _plane_from_formula(5, 12)
+    sums = o.harmonic_sums(P, g["j0"], g["n_harm"])
+    for cell in g["cells"]:
+        for H, v in cell["S"].items():
+            assert sums[int(H)][cell["j"], cell["R"]] == v, (cell, H)
+
+
+def test_harmonic_sum_invariants():
+    rng = np.random.default_rng(7)
+    P = rng.exponential(size=(33, 400))
+    j0 = 16
+    sums = o.harmonic_sums(P, j0, 16)
+    np.testing.assert_array_equal(sums[1], P)
+    c = np.full((33, 400), 2.5)
+    sc = o.harmonic_sums(c, j0, 16)
+    for H in (1, 2, 4, 8, 16):
+        np.testing.assert_allclose(sc[H], 2.5 * H)
+    # mirror symmetry in z
+    sm = o.harmonic_sums(P[::-1].copy(), j0, 16)
+    for H in (2, 4, 8, 16):
+        np.testing.assert_array_equal(sm[H], sums[H][::-1])
+    # stages nest: each stage contains the previous one plus non-negative terms
+    for H in (2, 4, 8, 16):
+        assert np.all(sums[H] >= sums[H // 2])
+
+
+def test_harmonic_sum_collects_a_pulsar_harmonic_comb():
+    """Harmonics h = 1..16 of a fundamental (r_f, m_f) at (h r_f, h m_f): the cell of
+    the H-th harmonic sums exactly the first H of them."""
+    nz, nb, j0 = 193, 4000, 96
+    for rf, mf in ((97, 3), (211, -5), (50, 0)):
+        P = np.zeros((nz, nb))
+        for h in range(1, 17):
+            P[j0 + h * mf, h * rf] += 1.0 + 0.01 * h
+        sums = o.harmonic_sums(P, j0, 16)
+        for H in (1, 2, 4, 8, 16):
+            want = sum(1.0 + 0.01 * h for h in range(1, H + 1))
+            assert abs(sums[H][j0 + H * mf, H * rf] - want) < 1e-12
+
+
+# ------------------------------------------------------------ thresholds
+
+def test_thresholds_closed_forms():
+    tail = 0.5 * math.erfc(6 / math.sqrt(2))
+    assert abs(o.threshold(1) - (-math.log(tail))) < 1e-9
+    for H in (1, 2, 4, 8, 16):
+        t = o.threshold(H)
+        q = math.exp(-t) * math.fsum(t ** k / math.factorial(k) for k in range(H))
+        assert abs(q / tail - 1) < 1e-9
+        assert abs(float(o.gaussian_sigma(t, H)) - 6.0) < 1e-8
+    assert all(o.threshold(2 * H) > o.threshold(H) for H in (1, 2, 4, 8))
+
+
+def test_gaussian_sigma_large_power_no_underflow():
+    s = o.gaussian_sigma(np.array([2000.0, 5000.0]), 16)
+    assert np.all(np.isfinite(s)) and s[1] > s[0] > 50
+
+
+def test_search_finds_injection_and_reports_fundamental():
+    n = 1 << 17
+    x = synth.make_series(n, [synth.Injection(0.05, 5000.0, 12.0, 0.5)], 3, 0)
+    s = o.normalise(o.spectrum(x), "median")
+    zs = o.z_grid(-16, 16, 2)
+    P = o.power_plane(s, zs)
+    c = o.search(P, zs, 4, r_lo=24, h_max=24)
+    best = max(c, key=lambda k: k.sigma)
+    assert best.harm == 1 and abs(best.r - 5006) <= 1 and abs(best.z - 12) <= 2
+    # noise-only: no candidate at 6 sigma expected in 1.1e6 cells x 3 stages
+    y = synth.make_series(n, [], 4, 0)
+    P0 = o.power_plane(o.normalise(o.spectrum(y), "median"), zs)
+    assert len(o.search(P0, zs, 4, r_lo=24, h_max=24)) <= 2
+
+
+# ------------------------------------------------------------ refinement
+
+def test_rz_power_reduces_to_bin_power():
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    for r in (50, 123, 300):
+        assert abs(o.rz_power(a, float(r), 0.0) - abs(a[r]) ** 2) < 1e-12
+
+
+def test_rz_power_half_bin_window_energy():
+    n, a = 1 << 17, 0.05
+    x = synth.chirp(n, synth.Injection(a, 5000.5, 0.0, 0.4))
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    k = np.arange(-15, 17) - 0.5
+    ew = np.sum(np.sinc(k) ** 2)
+    # y = sqrt(81.92) sum_k sinc(k - r)^2 over the window, so P = 81.92 * ew^2
+    assert abs(o.rz_power(s, 5000.5, 0.0) - 81.92 * ew * ew) < 2e-3 * 81.92
+
+
+def test_rz_gradients_match_central_differences():
+    n = 1 << 16
+    x = synth.make_series(n, [synth.Injection(0.08, 3000.0, 31.0, 0.4)], 5, 0)
+    s = o.normalise(o.spectrum(x), "median")
+    for r, z in ((3015.3, 30.2), (3016.1, 31.7), (2000.4, -12.3)):
+        p, gr, gz, ks, ga = o.rz_power_grad(s, r, z)
+        h = 1e-3
+        fr = (o.rz_power(s, r + h, z) - o.rz_power(s, r - h, z)) / (2 * h)
+        fz = (o.rz_power(s, r, z + h) - o.rz_power(s, r, z - h)) / (2 * h)
+        assert abs(gr - fr) < 1e-4 * max(1, abs(fr)) + 1e-5 * p
+        assert abs(gz - fz) < 1e-4 * max(1, abs(fz)) + 1e-5 * p
+        # dP/dA_k as d/dRe + i d/dIm, by finite differences on two bins
+        for idx in (3, len(ks) // 2):
+            k = ks[idx]
+            e = 1e-6
+            sp_ = s.copy(); sp_[k] += e
+            sm_ = s.copy(); sm_[k] -= e
+            dre = (o.rz_power(sp_, r, z) - o.rz_power(sm_, r, z)) / (2 * e)
+            sp_ = s.copy(); sp_[k] += 1j * e
+            sm_ = s.copy(); sm_[k] -= 1j * e
+            dim = (o.rz_power(sp_, r, z) - o.rz_power(sm_, r, z)) / (2 * e)
+            assert abs(ga[idx] - (dre + 1j * dim)) < 1e-5 * max(1, abs(ga[idx]))
+
+
+def test_refine_optimum_on_noise_free_signal():
+    n = 1 << 17
+    inj = synth.Injection(0.05, 4000.3, 14.6, 0.9)
+    x = synth.chirp(n, inj)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    r, z, p = o.refine_optimum(s, inj.r_mean + 0.3, inj.z - 0.5)
+    assert abs(r - inj.r_mean) < 0.01 and abs(z - inj.z) < 0.05
+    assert p > 0.95 * 81.92
+
+
+# ------------------------------------------------------------ error metric
+
+def test_power_errors_metric():
+    ref = np.array([0.5, 30.0, 100.0, 2.0])
+    test = ref * np.array([1.5, 1.01, 0.98, 1.0])
+    e = o.power_errors(test, ref, tau1=20.0)
+    assert e["n_det"] == 2
+    assert abs(e["max_rel_det"] - 0.02) < 1e-12
+    assert abs(e["max_abs"] - 2.0) < 1e-12
