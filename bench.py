@@ -1,0 +1,252 @@
+"""FDAS hot-path benchmark on one MI355X.
+
+One step = the whole hot path over one SKA-like series: real FFT and median
+normalisation, overlap-save correlation with 193 acceleration templates and the
+power plane, harmonic sums up to 16 and the 6-sigma threshold.  The series is
+N = 2^23 float32 samples (536.9 s at 64 us) with 8 injected accelerated
+sinusoids, already resident in HBM.  Throughput is bins x templates per second
+(N/2 * 193 per step).  The headline path stores spectrum, templates and plane
+in bfloat16 (FP32 arithmetic); the FP32-storage path is timed beside it.
+
+Prints one JSON line.  Extra legs: the FP64 oracle timed on a bounded sample
+of the same workload on the host (cpu_baseline), the power error of both paths
+against the oracle at detections, and the recall of the injections.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_FP32_VALU = 157.3e12  # flop/s, MI355X FP32 vector (packed; 78.6e12 unpacked)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--segment-len", type=int, default=8192)
+    ap.add_argument("--store", default="bf16")
+    ap.add_argument("--plane", default=None, help="plane dtype (default: same as --store)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage comparison leg")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle error/recall leg")
+    ap.add_argument("--n", type=int, default=1 << 23)
+    ap.add_argument("--calib-copy", action="store_true", help="also run a plain 1 GiB device copy (for counters)")
+    ap.add_argument("--json-out", default=None)
+    return ap.parse_args()
+
+
+def conv_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_conv.hip", "fft.hpp", "common.hpp", "launch.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2211_13517_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic(L, U, hmax, Z, nbins, store_bytes, plane_bytes):
+    """Per launch of the convolve->power kernel: bytes and flops the method needs.
+
+    Bytes: the spectrum read once, the template spectra read once, the plane
+    written once.  Flops (FFT convention 5 L log2 L per complex FFT): one forward
+    FFT per segment, and per segment and template a complex product (6 L), an
+    inverse FFT and |y|^2 of the U useful outputs (3 U)."""
+    nseg = math.ceil(nbins / U)
+    bytes_ = nbins * store_bytes + Z * L * store_bytes + Z * nbins * plane_bytes
+    fft = 5.0 * L * math.log2(L)
+    flops = nseg * fft + nseg * Z * (6.0 * L + fft + 3.0 * U)
+    return bytes_, flops
+
+
+def run_path(fdas, torch, xt, n, args, store, plane):
+    pl = fdas.Plan(store=store, plane=plane, n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, n_harmonics=16,
+                   segment_len=args.segment_len)
+    nb = n // 2
+    spec = pl.new_spectrum(nb)
+    P = pl.new_plane(nb)
+    cap = 1 << 20
+    cands = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        count.zero_()
+        pl.spectrum(xt, [0], [n], out=spec)
+        if ev is not None:
+            ev[0].record(stream)
+        pl.convolve_spectrum(spec, [n], plane=P)
+        if ev is not None:
+            ev[1].record(stream)
+        pl.harmonic_sum(P, [n], capacity=cap, cands=cands, count=count)
+
+    for _ in range(args.warmup):
+        step()
+    pl.check(count, cap)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    conv_ms = [a.elapsed_time(b) for a, b in evs]
+    pl.check(count, cap)
+    return dict(plan=pl, plane=P, spec=spec, cands=cands, count=int(count.item()), step_s=dt / args.steps,
+                conv_ms=float(np.mean(conv_ms)), conv_ms_all=conv_ms)
+
+
+def oracle_checks(o, synth, x, inj, res, Z):
+    """Relative power error at detections (sampled) and injection recall."""
+    zs = o.z_grid(-96, 96, 1)
+    taps, _ = o.template_taps(zs)
+    a = o.normalise(o.spectrum(x), "median")
+    nb = len(x) // 2
+    P = res["plane"].view(Z, nb)
+    # detections: every cell within +-3 bins and +-4 z of each injection's peak,
+    # plus cells above tau_1 found by the GPU (sampled)
+    rows, cols = [], []
+    for i in inj:
+        rc, jc = int(round(i.r_mean)), int(round(i.z + 96))
+        for dj in range(-4, 5):
+            for dr in range(-3, 4):
+                if 0 <= jc + dj < Z:
+                    rows.append(jc + dj)
+                    cols.append(rc + dr)
+    rows, cols = np.array(rows), np.array(cols)
+    ref = o.power_cells(a, taps, rows, cols)
+    got = P[torch_index(rows), torch_index(cols)].float().cpu().numpy().astype(np.float64)
+    det = ref >= o.threshold(1)
+    rel = np.abs(got - ref) / ref
+    c = fdas_cands(res)
+    found = 0
+    for i in inj:
+        ok = np.any((np.abs(c["r"] - i.r_mean) <= 1.0) & (np.abs(c["z"] - i.z) <= 1.0)) if len(c) else False
+        found += bool(ok)
+    return dict(n_det=int(det.sum()), max_rel=float(rel[det].max()), median_rel=float(np.median(rel[det])),
+                recall=found / len(inj))
+
+
+_torch = None
+
+
+def torch_index(a):
+    return _torch.from_numpy(np.asarray(a)).to("cuda")
+
+
+def fdas_cands(res):
+    import paper_2211_13517_amd as fdas
+    return fdas.candidates_to_numpy(res["cands"], res["count"])
+
+
+def cpu_baseline(o, x, rows=6):
+    """The oracle as it stands, timed on a bounded sample: spectrum and median
+    normalisation of the full series, then the correlation rows of `rows`
+    acceleration trials (numpy's FFT runs on one thread)."""
+    zs = o.z_grid(-96, 96, 1)
+    sel = np.linspace(0, len(zs) - 1, rows).round().astype(int)
+    t0 = time.perf_counter()
+    a = o.normalise(o.spectrum(x), "median")
+    o.power_plane(a, zs, rows=list(sel))
+    dt = time.perf_counter() - t0
+    nb = len(x) // 2
+    return dict(value=rows * nb / dt, unit="bins*templates/s", cores=1, kind="oracle",
+                sample=f"spectrum+median normalisation of one N={len(x)} series and {rows} of 193 template rows "
+                       f"(full-length FFT correlation, FP64, numpy single-threaded); {dt:.1f} s")
+
+
+def main():
+    global _torch
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md but not built)"}))
+        sys.exit(2)
+    import torch
+    _torch = torch
+    import paper_2211_13517_amd as fdas
+    import synth
+    fdas.load()
+    n = args.n
+    x, inj, _ = synth.ska_single(seed=2, n=n)
+    xt = torch.from_numpy(x).to("cuda")
+    plane_dt = args.plane or args.store
+    res = run_path(fdas, torch, xt, n, args, args.store, plane_dt)
+    pl = res["plan"]
+    Z, L, U, hmax = pl.Z, pl.L, pl.U, pl.hmax
+    nb = n // 2
+    bt = nb * Z
+    sb = 8 if args.store == "f32" else 4
+    pb = 4 if plane_dt == "f32" else 2
+    abytes, aflops = algorithmic(L, U, hmax, Z, nb, sb, pb)
+    conv_s = res["conv_ms"] / 1e3
+    out = {
+        "metric": "bins*templates/s for FDAS conv, BF16 vs FP32 at <=3% power err; HBM GB/s",
+        "value": bt / res["step_s"],
+        "unit": "bins*templates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["step_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"SKA-like single series: N=2^{int(math.log2(n))} float32, 8 injected accelerated "
+                               f"sinusoids, 193 templates z in [-96,96] step 1, segment {L}, median normalisation, "
+                               f"harmonic sums to 16, 6 sigma",
+                   "storage": args.store, "plane": plane_dt, "segment_len": L, "templates": Z,
+                   "bins": nb, "G": None},
+        "conv_only": {"bt_per_s": bt / conv_s, "ms": res["conv_ms"], "alg_GBps": abytes / conv_s / 1e9,
+                      "alg_TFLOPs": aflops / conv_s / 1e12},
+    }
+    # roofline of the dominant kernel (convolve->power)
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "conv_traffic.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        key = f"{args.store}/{plane_dt}/{L}/{n}"
+        if t.get("source_hash") == conv_source_hash() and key in t.get("per_launch_bytes", {}):
+            traffic = t["per_launch_bytes"][key]
+    out["roofline"] = {"bound": "alu", "achieved": aflops / conv_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                       "unit": "TFLOP/s", "frac": aflops / conv_s / PEAK_FP32_VALU, "traffic": traffic,
+                       "hbm_alg_GBps": abytes / conv_s / 1e9, "hbm_frac": abytes / conv_s / PEAK_HBM}
+    if not args.no_fp32:
+        r32 = run_path(fdas, torch, xt, n, args, "f32", "f32")
+        out["fp32"] = {"value": bt / r32["step_s"], "ms_per_step": r32["step_s"] * 1e3,
+                       "conv_bt_per_s": bt / (r32["conv_ms"] / 1e3), "conv_ms": r32["conv_ms"]}
+        out["speedup_vs_fp32"] = {"step": r32["step_s"] / res["step_s"], "conv": r32["conv_ms"] / res["conv_ms"]}
+    if not args.no_check:
+        from oracle import fdas64 as o
+        out["accuracy"] = {args.store: oracle_checks(o, synth, x, inj, res, Z)}
+        if not args.no_fp32:
+            out["accuracy"]["f32"] = oracle_checks(o, synth, x, inj, r32, Z)
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        from oracle import fdas64 as o
+        out["cpu_baseline"] = cpu_baseline(o, x)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * fdas.h - C ABI of the MI355X (gfx950) Fourier Domain Acceleration Search hot path.
+ *
+ * The method: the paper's section 2.1 ("FDAS") describes a matched filter that
+ * correlates the spectrum of each dedispersed time series with templates of
+ * constant acceleration, so the cost grows linearly with the number of
+ * acceleration trials; section 2.2 ("Mixed-Precision") performs that
+ * correlation in the frequency domain with FFTs, stores the data of this
+ * convolution stage in bfloat16 and keeps the arithmetic in FP32; section 3
+ * ("Results") sets the SKA-like workload (600 s at 64 us, 5925 DM trials of
+ * which 3050 at full time resolution, 193 acceleration trials).  The
+ * harmonic-summing stage that follows the correlation is cited in the
+ * introduction.  Formulas that the paper leaves implicit are stated at each
+ * entry point below.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Ownership: every data pointer is caller-owned DEVICE memory on the plan's
+ *    device unless stated otherwise; the library allocates no device memory.
+ *    Its scratch space is one caller-allocated workspace (fdas_query, then
+ *    fdas_set_workspace).  Host arrays (offsets, lengths, outputs named
+ *    *_host) are read or written before the call returns.
+ *  - Asynchrony: work is enqueued on the plan's HIP stream and the call returns
+ *    without waiting, except where stated (fdas_check, fdas_copy_thresholds).
+ *  - Errors: arguments are checked before anything is enqueued; a failed check
+ *    returns a non-zero fdas_status, enqueues nothing and sets the plan's
+ *    message (fdas_last_error).  A HIP launch error returns FDAS_ERR_HIP.
+ *    Conditions detected on the device (non-finite spectrum, candidate buffer
+ *    overflow) are latched in the workspace and reported by fdas_check.
+ *    No C++ exception crosses this interface and nothing aborts.
+ *  - Threading: a plan is used by one host thread at a time; plans are
+ *    independent of each other.
+ *  - Complex values are (re, im) pairs of the storage type: FDAS_F32 8 bytes,
+ *    FDAS_BF16 and FDAS_F16 4 bytes (re in the low half), rounded to nearest
+ *    even on conversion.
+ *  - Batches: series are float32, given by device pointer `series` plus host
+ *    arrays offsets[i] (first sample of series i in `series`) and lengths[i]
+ *    (its length N_i: n_samples, n_samples/2 or n_samples/4, i.e. full
+ *    resolution or 2x/4x decimated DM trials).  Spectra are packed in series
+ *    order, series i starting at complex element S_i = sum_{k<i} N_k/2.  Power
+ *    planes are packed the same way, series i starting at element Z*S_i and
+ *    laid out z-major: plane_i[j][r], j < Z acceleration trials, r < N_i/2.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdas_plan_s *fdas_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+  FDAS_OK = 0,
+  FDAS_ERR_ARG = 1,         /* invalid argument or size */
+  FDAS_ERR_NOMEM = 2,       /* workspace or output buffer too small */
+  FDAS_ERR_HIP = 3,         /* HIP runtime error */
+  FDAS_ERR_UNSUPPORTED = 4, /* valid but not built (e.g. a segment length) */
+  FDAS_ERR_OVERFLOW = 5,    /* more candidates than the buffer holds */
+  FDAS_ERR_NONFINITE = 6,   /* NaN or Inf in a spectrum */
+  FDAS_ERR_STATE = 7        /* call out of order (no workspace, no templates) */
+} fdas_status;
+
+typedef enum { FDAS_F32 = 0, FDAS_BF16 = 1, FDAS_F16 = 2 } fdas_dtype;
+
+typedef enum { FDAS_NORM_NONE = 0, FDAS_NORM_VARIANCE = 1, FDAS_NORM_MEDIAN = 2 } fdas_norm;
+
+typedef struct {
+  int64_t n_samples;         /* N of the longest series: a power of two, 2^17 .. 2^23 */
+  int64_t max_batch_samples; /* largest sum of lengths per call; 0 means n_samples */
+  double tsamp;              /* sampling time in s (metadata: f = r/T, fdot = z/T^2, T = N tsamp) */
+  double z_min, z_max, z_step; /* acceleration trials z_j = z_min + j z_step in bins, z_min = -z_max */
+  int32_t n_harmonics;       /* highest harmonic summed: 1, 2, 4, 8 or 16 */
+  int32_t kernel_margin;     /* m: template half-width h(z) = ceil(|z|/2) + m bins (default 16) */
+  int32_t segment_len;       /* overlap-save FFT length L: 1024, 2048, 4096 or 8192; 0 = 1024 */
+  int32_t store_dtype;       /* fdas_dtype of spectra and template spectra */
+  int32_t plane_dtype;       /* fdas_dtype of the power plane */
+  int32_t norm;              /* fdas_norm */
+  int32_t norm_block;        /* bins per median block B (power of two, divides N/2; default 2048) */
+  double noise_var;          /* sigma^2 for FDAS_NORM_VARIANCE */
+  double sigma_threshold;    /* Gaussian-equivalent detection threshold (default 6) */
+  int32_t r_lo;              /* lowest fundamental bin searched; 0 means h_max */
+  int32_t templates_per_tile; /* templates one wavefront runs per loaded segment; 0 = automatic */
+} fdas_params;
+
+/* One detection: 32 bytes. harm is the number of harmonics summed (H), R and j
+ * the cell of the H-th harmonic (bin, acceleration-trial index), r = R/H and
+ * z = z_j/H the fundamental, power the harmonic sum S_H, sigma its
+ * Gaussian-equivalent significance. */
+typedef struct {
+  int32_t series, harm, R, j;
+  float r, z, power, sigma;
+} fdas_candidate;
+
+/* Fills *p with defaults (margin 16, L 1024, FP32 storage and plane, median
+ * normalisation with B = 2048, 6 sigma, 16 harmonics, z in [-96, 96] step 1,
+ * N = 2^23, tsamp 64 us).  Never fails for a non-NULL p. */
+fdas_status fdas_default_params(fdas_params *p);
+
+/* Validates *params and creates a plan bound to `device` and the HIP stream
+ * `hip_stream` (NULL = default stream).  Derived sizes: Z = (z_max - z_min)/z_step + 1,
+ * h_max = ceil(z_max/2) + m, U = L - 2 h_max outputs per segment.  Thresholds
+ * tau_H solve P(Gamma(H,1) > tau_H) = P(N(0,1) > sigma_threshold) in FP64: a
+ * noise harmonic sum of H unit-mean exponential powers is Gamma(H,1).
+ * On failure *out is NULL and the message is available from fdas_last_error(NULL). */
+fdas_status fdas_plan(const fdas_params *params, int device, void *hip_stream, fdas_plan_t *out);
+
+/* Workspace bytes the plan needs (templates, FFT scratch for max_batch_samples,
+ * twiddle tables, device status), and the derived L, h_max and Z.  Any output
+ * pointer may be NULL. */
+fdas_status fdas_query(fdas_plan_t plan, int64_t *workspace_bytes, int32_t *L, int32_t *h_max, int32_t *Z);
+
+/* Binds caller-allocated device memory (256-byte aligned, at least the queried
+ * size) as the plan's workspace.  The plan keeps the pointer, never frees it;
+ * binding a new workspace discards templates made in the old one. */
+fdas_status fdas_set_workspace(fdas_plan_t plan, void *dev_ptr, int64_t bytes);
+
+/* Builds the template bank on the device in FP64 (section 2.1's matched-filter
+ * templates, one per acceleration trial):
+ *   rho(q, z) = int_0^1 exp(-2 pi i q u + i pi z (u - 1/2)^2) du  (Fresnel integrals),
+ *   t_q(z_j) = conj(rho(q, z_j)) / sqrt(E_j) for |q| <= h(z_j), E_j = sum |rho|^2,
+ * and their length-L spectra T_j[k] = (1/L) sum_q t_q exp(+2 pi i k q / L)
+ * (the 1/L of the inverse FFT folded in), stored in store_dtype.
+ * Needs a workspace.  Must run before fdas_convolve*. */
+fdas_status fdas_make_templates(fdas_plan_t plan);
+
+/* Rows a1-a2: real FFT of every series, A_r = sum_n x_n exp(-2 pi i r n/N) for
+ * r < N/2 (Nyquist dropped, A_0 set to 0), then normalisation: NONE; VARIANCE
+ * A/sqrt(N sigma^2); MEDIAN A sqrt(ln2/m_b) with m_b the lower median of |A|^2
+ * (rank (B-1)/2) in each block of B bins (a zero median scales the block by 0).
+ * spectrum_out: store_dtype complex, packed as described above. */
+fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
+                          const int64_t *lengths_host, int32_t n_series, void *spectrum_out);
+
+/* Rows a4-a8 from a normalised spectrum (store_dtype, packed): overlap-save
+ * segments of L bins starting at s U - h_max (zero outside [0, N/2)), one
+ * forward FFT per segment, then for every template j: product with T_j,
+ * inverse FFT, and P[j][s U + i] = |y[h_max + i]|^2 for i < U, i.e.
+ *   P[j][r] = | sum_{q=-h_max}^{h_max} A'_{r+q} t_q(z_j) |^2,
+ * written to plane_out (plane_dtype, packed z-major).  plane_bytes is the
+ * size of plane_out and must cover the whole batch. */
+fdas_status fdas_convolve_spectrum(fdas_plan_t plan, const void *spectrum, const int64_t *lengths_host,
+                                   int32_t n_series, void *plane_out, int64_t plane_bytes);
+
+/* Rows a1-a8 in one call: fdas_spectrum then fdas_convolve_spectrum.
+ * spectrum_out may be NULL, in which case the spectrum lives in the workspace. */
+fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
+                          const int64_t *lengths_host, int32_t n_series, void *spectrum_out,
+                          void *plane_out, int64_t plane_bytes);
+
+/* Rows a9-a10: nested harmonic sums and thresholding over a packed plane.
+ * For cell (R, j) with m = j - j0 (j0 the z = 0 trial) and H the top stage,
+ *   S_H(R, j) = sum_{k=1}^{H} P[j0 + sgn(m) floor((2k|m| + H)/(2H))][floor((2kR + H)/(2H))],
+ * and the lower stages H' use the terms k = H/H', 2H/H', ..., H.  A cell is
+ * searched at stage H' if R >= H' r_lo and R < N/2 - h_max, passes if
+ * S_{H'} >= tau_{H'}, and emits one record for its most significant passing
+ * stage.  Records are appended at atomically reserved indices of `cands`
+ * (device, `capacity` records, order not deterministic); *d_count (device
+ * int64, zeroed by the caller before the first call of a search) counts every
+ * passing cell, also those that did not fit. */
+fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t *lengths_host,
+                              int32_t n_series, fdas_candidate *cands, int64_t capacity,
+                              int64_t *d_count);
+
+/* Waits for the plan's stream, then reports device-side conditions latched
+ * since the last fdas_check: FDAS_ERR_NONFINITE if a spectrum held NaN/Inf,
+ * FDAS_ERR_OVERFLOW if d_count (optional, device) exceeds capacity. Clears
+ * the latch. */
+fdas_status fdas_check(fdas_plan_t plan, const int64_t *d_count, int64_t capacity);
+
+/* Copies the FP64 template taps (complex128 [Z][2 h_max + 1], column q + h_max)
+ * and/or the template spectra (store_dtype complex [Z][L]) into device buffers;
+ * either pointer may be NULL.  For inspection and tests. */
+fdas_status fdas_copy_templates(fdas_plan_t plan, void *taps_out, void *spectra_out);
+
+/* Writes the thresholds tau_H for H = 1, 2, 4, ... n_harmonics to the host
+ * array tau_host (log2(n_harmonics)+1 values). */
+fdas_status fdas_copy_thresholds(fdas_plan_t plan, double *tau_host);
+
+/* Self-test hook of the FFT engine: `batch` independent complex FFTs of
+ * length L (256 ... 8192) from `in` to `out` (device, complex64, contiguous),
+ * direction -1: X_k = sum_n x_n exp(-2 pi i k n / L), +1: the unnormalised
+ * inverse.  Uses the plan's stream and twiddle tables (needs a workspace). */
+fdas_status fdas_test_fft(fdas_plan_t plan, int32_t L, int32_t direction, const void *in, void *out, int64_t batch);
+
+/* Releases the plan (not the workspace, which the caller owns). NULL is allowed. */
+fdas_status fdas_plan_destroy(fdas_plan_t plan);
+
+/* Message of the last failed call on `plan`, or of the last failed
+ * fdas_plan() when plan is NULL.  Valid until the next call on that plan. */
+const char *fdas_last_error(fdas_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDAS_H */

@@ -1,0 +1,257 @@
+"""Python binding of libfdas (MI355X Fourier Domain Acceleration Search hot path).
+
+Argument marshalling only: every step of the search runs in the HIP kernels of
+``libfdas.so``.  PyTorch supplies device memory and the HIP stream.  There is
+no CPU fallback: if the shared library is missing, ``load()`` raises.
+
+Layouts (see include/fdas.h):
+  * series: float32 1-D device tensor, series i at offsets[i], length lengths[i]
+  * spectrum: packed complex bins; F32 -> float32 [bins, 2], BF16 -> bfloat16
+    [bins, 2], F16 -> float16 [bins, 2] (re, im)
+  * plane: packed z-major power planes, F32/BF16/F16 1-D
+  * candidates: int32 [capacity, 8] (series, harm, R, j, then r, z, power,
+    sigma as float32 bits); ``candidates_to_numpy`` decodes them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdas.so")
+
+F32, BF16, F16 = 0, 1, 2
+DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
+NORMS = {"none": 0, "variance": 1, "median": 2}
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED",
+          5: "ERR_OVERFLOW", 6: "ERR_NONFINITE", 7: "ERR_STATE"}
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fdas {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_samples", c_int64), ("max_batch_samples", c_int64), ("tsamp", c_double),
+                ("z_min", c_double), ("z_max", c_double), ("z_step", c_double),
+                ("n_harmonics", c_int32), ("kernel_margin", c_int32), ("segment_len", c_int32),
+                ("store_dtype", c_int32), ("plane_dtype", c_int32), ("norm", c_int32),
+                ("norm_block", c_int32), ("noise_var", c_double), ("sigma_threshold", c_double),
+                ("r_lo", c_int32), ("templates_per_tile", c_int32)]
+
+
+EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace", "fdas_make_templates",
+           "fdas_spectrum", "fdas_convolve_spectrum", "fdas_convolve", "fdas_harmonic_sum", "fdas_check",
+           "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
+           "fdas_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libfdas.so (built by ``paper_2211_13517_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2211_13517_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "fdas_default_params": ([POINTER(Params)], c_int),
+        "fdas_plan": ([POINTER(Params), c_int, P, POINTER(P)], c_int),
+        "fdas_query": ([P, POINTER(c_int64), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)], c_int),
+        "fdas_set_workspace": ([P, P, c_int64], c_int),
+        "fdas_make_templates": ([P], c_int),
+        "fdas_spectrum": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P], c_int),
+        "fdas_convolve_spectrum": ([P, P, POINTER(c_int64), c_int32, P, c_int64], c_int),
+        "fdas_convolve": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64], c_int),
+        "fdas_harmonic_sum": ([P, P, POINTER(c_int64), c_int32, P, c_int64, P], c_int),
+        "fdas_check": ([P, P, c_int64], c_int),
+        "fdas_copy_templates": ([P, P, P], c_int),
+        "fdas_copy_thresholds": ([P, POINTER(c_double)], c_int),
+        "fdas_test_fft": ([P, c_int32, c_int32, P, P, c_int64], c_int),
+        "fdas_plan_destroy": ([P], c_int),
+        "fdas_last_error": ([P], c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _i64(values: Sequence[int]):
+    a = (c_int64 * len(values))(*[int(v) for v in values])
+    return a
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def plane_torch_dtype(dt: int):
+    import torch
+    return {F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[dt]
+
+
+def spectrum_torch_dtype(dt: int):
+    return plane_torch_dtype(dt)
+
+
+class Plan:
+    """One search configuration on one GPU (the torch current stream at creation).
+
+    Keyword parameters follow ``fdas_params`` (include/fdas.h); ``store`` and
+    ``plane`` take "f32"/"bf16"/"f16", ``norm`` takes "none"/"variance"/"median".
+    """
+
+    def __init__(self, device: int = 0, store: str = "f32", plane: str = "f32", norm: str = "median",
+                 make_templates: bool = True, **kw):
+        import torch
+        self.lib = load()
+        p = Params()
+        self._check(self.lib.fdas_default_params(byref(p)), None)
+        p.store_dtype = DTYPES[store]
+        p.plane_dtype = DTYPES[plane]
+        p.norm = NORMS[norm]
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(p, k, v)
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        st = self.lib.fdas_plan(byref(p), device, c_void_p(self.stream.cuda_stream), byref(h))
+        if st != 0:
+            raise FdasError(st, self.lib.fdas_last_error(None).decode())
+        self.handle = h
+        self.params = p
+        ws, L, hmax, Z = c_int64(), c_int32(), c_int32(), c_int32()
+        self._check(self.lib.fdas_query(h, byref(ws), byref(L), byref(hmax), byref(Z)))
+        self.ws_bytes, self.L, self.hmax, self.Z = ws.value, L.value, hmax.value, Z.value
+        self.U = self.L - 2 * self.hmax
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.fdas_set_workspace(h, c_void_p(self.workspace.data_ptr()), self.ws_bytes))
+        self.store_dtype, self.plane_dtype = p.store_dtype, p.plane_dtype
+        self.n_harmonics = p.n_harmonics
+        if make_templates:
+            self.make_templates()
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, st: int, h="self"):
+        if st != 0:
+            hh = self.handle if h == "self" else h
+            raise FdasError(st, self.lib.fdas_last_error(hh).decode())
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.fdas_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_stages(self) -> int:
+        return int(np.log2(self.n_harmonics)) + 1
+
+    def z_values(self) -> np.ndarray:
+        return self.params.z_min + self.params.z_step * np.arange(self.Z, dtype=np.float64)
+
+    # ------------------------------------------------------------------ calls
+    def make_templates(self):
+        self._check(self.lib.fdas_make_templates(self.handle))
+
+    def templates(self):
+        """(taps complex128 [Z][2 h_max + 1], spectra [Z][L][2] in the storage dtype), on the GPU."""
+        import torch
+        taps = torch.empty((self.Z, 2 * self.hmax + 1), dtype=torch.complex128, device=self.device)
+        spec = torch.empty((self.Z, self.L, 2), dtype=spectrum_torch_dtype(self.store_dtype), device=self.device)
+        self._check(self.lib.fdas_copy_templates(self.handle, c_void_p(taps.data_ptr()), c_void_p(spec.data_ptr())))
+        return taps, spec
+
+    def thresholds(self) -> np.ndarray:
+        out = (c_double * self.n_stages)()
+        self._check(self.lib.fdas_copy_thresholds(self.handle, out))
+        return np.array(out[:], dtype=np.float64)
+
+    def new_spectrum(self, total_bins: int):
+        import torch
+        return torch.empty((total_bins, 2), dtype=spectrum_torch_dtype(self.store_dtype), device=self.device)
+
+    def new_plane(self, total_bins: int):
+        import torch
+        return torch.empty(self.Z * total_bins, dtype=plane_torch_dtype(self.plane_dtype), device=self.device)
+
+    def spectrum(self, series, offsets: Sequence[int], lengths: Sequence[int], out=None):
+        total = int(sum(lengths)) // 2
+        out = self.new_spectrum(total) if out is None else out
+        self._check(self.lib.fdas_spectrum(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
+                                           len(lengths), c_void_p(out.data_ptr())))
+        return out
+
+    def convolve_spectrum(self, spectrum, lengths: Sequence[int], plane=None):
+        total = int(sum(lengths)) // 2
+        plane = self.new_plane(total) if plane is None else plane
+        nbytes = plane.numel() * plane.element_size()
+        self._check(self.lib.fdas_convolve_spectrum(self.handle, c_void_p(spectrum.data_ptr()), _i64(lengths),
+                                                    len(lengths), c_void_p(plane.data_ptr()), nbytes))
+        return plane
+
+    def convolve(self, series, offsets: Sequence[int], lengths: Sequence[int], plane=None, spectrum=None):
+        total = int(sum(lengths)) // 2
+        plane = self.new_plane(total) if plane is None else plane
+        nbytes = plane.numel() * plane.element_size()
+        sp = None if spectrum is None else c_void_p(spectrum.data_ptr())
+        self._check(self.lib.fdas_convolve(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
+                                           len(lengths), sp, c_void_p(plane.data_ptr()), nbytes))
+        return plane
+
+    def harmonic_sum(self, plane, lengths: Sequence[int], capacity: int = 1 << 20, cands=None, count=None):
+        """Appends candidates; returns (cands int32 [capacity, 8], count int64 [1]) on the GPU."""
+        import torch
+        if cands is None:
+            cands = torch.empty((max(capacity, 1), 8), dtype=torch.int32, device=self.device)
+        if count is None:
+            count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self._check(self.lib.fdas_harmonic_sum(self.handle, c_void_p(plane.data_ptr()), _i64(lengths), len(lengths),
+                                               c_void_p(cands.data_ptr()), capacity, c_void_p(count.data_ptr())))
+        return cands, count
+
+    def check(self, count=None, capacity: int = 0):
+        """Synchronises and raises FdasError for latched device conditions."""
+        self._check(self.lib.fdas_check(self.handle, None if count is None else c_void_p(count.data_ptr()), capacity))
+
+    def test_fft(self, x, direction: int):
+        """Batched complex FFT of length L through the library's FFT engine (self-test)."""
+        import torch
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        L = x.shape[-1]
+        self._check(self.lib.fdas_test_fft(self.handle, L, direction, c_void_p(x.data_ptr()),
+                                           c_void_p(out.data_ptr()), x.numel() // L))
+        return out
+
+
+CAND_FIELDS = ("series", "harm", "R", "j", "r", "z", "power", "sigma")
+
+
+def candidates_to_numpy(cands, count: int) -> np.ndarray:
+    """Decodes the first ``count`` records into a numpy structured array."""
+    n = min(int(count), cands.shape[0])
+    raw = cands[:n].cpu().numpy()
+    dt = np.dtype([(f, "<i4") for f in CAND_FIELDS[:4]] + [(f, "<f4") for f in CAND_FIELDS[4:]])
+    return raw.view(dt).reshape(-1)

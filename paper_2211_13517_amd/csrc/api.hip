@@ -1,0 +1,572 @@
+// C ABI of the FDAS library: plan validation, thresholds, workspace layout,
+// batch descriptors and kernel launches.  No device memory is allocated here:
+// the caller binds one workspace and passes every data buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+
+using namespace fdas;
+
+namespace {
+
+constexpr int kFftSizes[] = {256, 512, 1024, 2048, 4096, 8192};
+constexpr int kNumFftSizes = 6;
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int log2i(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+int cbytes(int dt) { return dt == FDAS_F32 ? 8 : 4; }
+int rbytes(int dt) { return dt == FDAS_F32 ? 4 : 2; }
+
+thread_local std::string g_plan_error;
+
+// ln P(Gamma(h,1) > x) for integer h (closed form of the upper incomplete gamma)
+double log_tail_gamma_host(double x, int h) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < h; ++k) {
+    term *= x / k;
+    sum += term;
+  }
+  return -x + std::log(sum);
+}
+
+// tau with P(Gamma(h,1) > tau) = P(N(0,1) > sigma), by bisection in log space.
+double threshold_for(int h, double sigma) {
+  const double target = std::log(0.5 * std::erfc(sigma / std::sqrt(2.0)));
+  double lo = 0.0, hi = 10.0;
+  while (log_tail_gamma_host(hi, h) > target) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (log_tail_gamma_host(mid, h) > target) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+struct LengthClass {
+  int64_t nsamp;
+  int M1, M2;
+  int list_off, count;
+};
+
+}  // namespace
+
+struct fdas_plan_s {
+  fdas_params p{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int Z = 0, j0 = 0, hmax = 0, K = 0, L = 0, U = 0, nstages = 0;
+  double tau[5] = {0, 0, 0, 0, 0};
+  int64_t max_batch = 0;
+  int max_series = 0;
+  int cu_count = 0;
+  // workspace layout (byte offsets)
+  char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  int64_t off_status = 0, off_tw[kNumFftSizes] = {}, off_exptab = 0, off_taps = 0, off_tspec = 0, off_desc = 0,
+          off_lists = 0, off_Y = 0, off_Zb = 0, off_spec = 0, total = 0;
+  bool templates_ready = false;
+  std::string err;
+  // current batch
+  std::vector<SeriesDesc> desc;
+  std::vector<int32_t> lists;
+  std::vector<LengthClass> classes;
+  std::vector<int64_t> key_offsets, key_lengths;
+  int64_t total_bins = 0, n_tiles = 0, max_bins = 0;
+  int G = 1;
+  bool batch_valid = false;
+  SeriesDesc* h_desc_pinned = nullptr;
+  int32_t* h_lists_pinned = nullptr;
+
+  fdas_status fail(fdas_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  const c32* tw(int L_) const {
+    for (int i = 0; i < kNumFftSizes; ++i)
+      if (kFftSizes[i] == L_) return reinterpret_cast<const c32*>(ws + off_tw[i]);
+    return nullptr;
+  }
+};
+
+static fdas_status hip_fail(fdas_plan_t pl, hipError_t e, const char* what) {
+  return pl->fail(FDAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+extern "C" {
+
+fdas_status fdas_default_params(fdas_params* p) {
+  if (!p) return FDAS_ERR_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->n_samples = int64_t(1) << 23;
+  p->tsamp = 64e-6;
+  p->z_min = -96.0;
+  p->z_max = 96.0;
+  p->z_step = 1.0;
+  p->n_harmonics = 16;
+  p->kernel_margin = 16;
+  p->segment_len = 0;
+  p->store_dtype = FDAS_F32;
+  p->plane_dtype = FDAS_F32;
+  p->norm = FDAS_NORM_MEDIAN;
+  p->norm_block = 2048;
+  p->noise_var = 1.0;
+  p->sigma_threshold = 6.0;
+  return FDAS_OK;
+}
+
+fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, fdas_plan_t* out) {
+  if (out) *out = nullptr;
+  auto bad = [](const std::string& m) {
+    g_plan_error = m;
+    return FDAS_ERR_ARG;
+  };
+  if (!params || !out) return bad("params and out must be non-NULL");
+  const fdas_params& p = *params;
+  if (!is_pow2(p.n_samples) || p.n_samples < (1 << 17) || p.n_samples > (1 << 23))
+    return bad("n_samples must be a power of two in [2^17, 2^23]");
+  const int64_t mb = p.max_batch_samples ? p.max_batch_samples : p.n_samples;
+  if (mb < p.n_samples) return bad("max_batch_samples must be 0 or >= n_samples");
+  if (!(p.z_step > 0) || !(p.z_max >= 0) || std::fabs(p.z_min + p.z_max) > 1e-9 * std::max(1.0, p.z_max))
+    return bad("z grid must be symmetric (z_min = -z_max) with z_step > 0");
+  const double zn = (p.z_max - p.z_min) / p.z_step;
+  if (std::fabs(zn - std::round(zn)) > 1e-9 || std::fabs(p.z_max / p.z_step - std::round(p.z_max / p.z_step)) > 1e-9)
+    return bad("z_max / z_step must be an integer");
+  const int Z = (int)std::llround(zn) + 1;
+  if (Z > 4096) return bad("at most 4096 acceleration trials");
+  if (!(p.n_harmonics == 1 || p.n_harmonics == 2 || p.n_harmonics == 4 || p.n_harmonics == 8 || p.n_harmonics == 16))
+    return bad("n_harmonics must be 1, 2, 4, 8 or 16");
+  const int margin = p.kernel_margin ? p.kernel_margin : 16;
+  if (margin < 1 || margin > 256) return bad("kernel_margin must be in [1, 256]");
+  const int hmax = (int)std::ceil(p.z_max / 2.0) + margin;
+  const int L = p.segment_len ? p.segment_len : 1024;
+  if (!(L == 1024 || L == 2048 || L == 4096 || L == 8192)) return bad("segment_len must be 0, 1024, 2048, 4096 or 8192");
+  if (4 * hmax > L) return bad("segment_len must be at least 4 * h_max (h_max = ceil(z_max/2) + margin)");
+  for (int dt : {p.store_dtype, p.plane_dtype})
+    if (dt < FDAS_F32 || dt > FDAS_F16) return bad("store_dtype / plane_dtype must be FDAS_F32, FDAS_BF16 or FDAS_F16");
+  if (p.norm < FDAS_NORM_NONE || p.norm > FDAS_NORM_MEDIAN) return bad("unknown norm");
+  const int B = p.norm_block ? p.norm_block : 2048;
+  if (!is_pow2(B) || B < 256 || B > 4096) return bad("norm_block must be a power of two in [256, 4096]");
+  if (p.norm == FDAS_NORM_VARIANCE && !(p.noise_var > 0)) return bad("noise_var must be > 0");
+  const double sig = p.sigma_threshold ? p.sigma_threshold : 6.0;
+  if (!(sig > 0 && sig < 30)) return bad("sigma_threshold must be in (0, 30)");
+  if (p.r_lo < 0) return bad("r_lo must be >= 0");
+  if (p.templates_per_tile < 0) return bad("templates_per_tile must be >= 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return bad("invalid device");
+
+  fdas_plan_s* pl = new (std::nothrow) fdas_plan_s();
+  if (!pl) return bad("out of host memory");
+  pl->p = p;
+  pl->p.max_batch_samples = mb;
+  pl->p.kernel_margin = margin;
+  pl->p.segment_len = L;
+  pl->p.norm_block = B;
+  pl->p.sigma_threshold = sig;
+  pl->device = device;
+  pl->stream = (hipStream_t)hip_stream;
+  pl->Z = Z;
+  pl->j0 = (int)std::llround(-p.z_min / p.z_step);
+  pl->hmax = hmax;
+  pl->K = 2 * hmax + 1;
+  pl->L = L;
+  pl->U = L - 2 * hmax;
+  pl->nstages = log2i(p.n_harmonics) + 1;
+  if (pl->p.r_lo == 0) pl->p.r_lo = hmax;
+  for (int i = 0; i < pl->nstages; ++i) pl->tau[i] = threshold_for(1 << i, sig);
+  pl->max_batch = mb;
+  pl->max_series = (int)(mb / (p.n_samples / 4));
+  hipDeviceGetAttribute(&pl->cu_count, hipDeviceAttributeMultiprocessorCount, device);
+  if (pl->cu_count <= 0) pl->cu_count = 256;
+
+  // workspace layout
+  int64_t o = 0;
+  pl->off_status = o;
+  o += 256;
+  for (int i = 0; i < kNumFftSizes; ++i) {
+    pl->off_tw[i] = o;
+    o = align256(o + (int64_t)twiddle_table_size(kFftSizes[i]) * (int64_t)sizeof(c32));
+  }
+  pl->off_exptab = o;
+  o = align256(o + (int64_t)L * 16);
+  pl->off_taps = o;
+  o = align256(o + (int64_t)Z * pl->K * 16);
+  pl->off_tspec = o;
+  o = align256(o + (int64_t)Z * L * cbytes(p.store_dtype));
+  pl->off_desc = o;
+  o = align256(o + (int64_t)pl->max_series * (int64_t)sizeof(SeriesDesc));
+  pl->off_lists = o;
+  o = align256(o + (int64_t)pl->max_series * 4);
+  pl->off_Y = o;
+  o = align256(o + mb / 2 * 8);
+  pl->off_Zb = o;
+  o = align256(o + mb / 2 * 8);
+  pl->off_spec = o;
+  o = align256(o + mb / 2 * cbytes(p.store_dtype));
+  pl->total = o;
+
+  if (hipHostMalloc((void**)&pl->h_desc_pinned, sizeof(SeriesDesc) * pl->max_series) != hipSuccess ||
+      hipHostMalloc((void**)&pl->h_lists_pinned, sizeof(int32_t) * pl->max_series) != hipSuccess) {
+    if (pl->h_desc_pinned) hipHostFree(pl->h_desc_pinned);
+    delete pl;
+    return bad("could not allocate pinned host staging");
+  }
+  *out = pl;
+  return FDAS_OK;
+}
+
+fdas_status fdas_query(fdas_plan_t pl, int64_t* ws, int32_t* L, int32_t* hmax, int32_t* Z) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (ws) *ws = pl->total;
+  if (L) *L = pl->L;
+  if (hmax) *hmax = pl->hmax;
+  if (Z) *Z = pl->Z;
+  return FDAS_OK;
+}
+
+fdas_status fdas_set_workspace(fdas_plan_t pl, void* dev_ptr, int64_t bytes) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!dev_ptr || bytes < pl->total) return pl->fail(FDAS_ERR_NOMEM, "workspace missing or smaller than fdas_query's size");
+  if (((uintptr_t)dev_ptr) & 255) return pl->fail(FDAS_ERR_ARG, "workspace must be 256-byte aligned");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  pl->ws = (char*)dev_ptr;
+  pl->ws_bytes = bytes;
+  pl->templates_ready = false;
+  pl->batch_valid = false;
+  std::vector<c32> tab;
+  for (int i = 0; i < kNumFftSizes; ++i) {
+    const int n = twiddle_table_size(kFftSizes[i]);
+    tab.assign(n, c32{0.f, 0.f});
+    twiddle_table_fill(kFftSizes[i], tab.data());
+    e = hipMemcpyAsync(pl->ws + pl->off_tw[i], tab.data(), n * sizeof(c32), hipMemcpyHostToDevice, pl->stream);
+    if (e != hipSuccess) return hip_fail(pl, e, "twiddle upload");
+    e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) return hip_fail(pl, e, "twiddle upload");
+  }
+  e = hipMemsetAsync(pl->ws + pl->off_status, 0, 256, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "status clear");
+  e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "status clear");
+  return FDAS_OK;
+}
+
+fdas_status fdas_make_templates(fdas_plan_t pl) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  c64* tab = reinterpret_cast<c64*>(pl->ws + pl->off_exptab);
+  c64* taps = reinterpret_cast<c64*>(pl->ws + pl->off_taps);
+  if ((e = launch_exp_table(pl->L, tab, pl->stream)) != hipSuccess) return hip_fail(pl, e, "exp table");
+  if ((e = launch_template_taps(pl->p.z_min, pl->p.z_step, pl->Z, pl->p.kernel_margin, pl->hmax, taps, pl->stream)) !=
+      hipSuccess)
+    return hip_fail(pl, e, "template taps");
+  if ((e = launch_template_spectra(pl->p.store_dtype, taps, tab, pl->Z, pl->hmax, pl->L, pl->ws + pl->off_tspec,
+                                   pl->stream)) != hipSuccess)
+    return hip_fail(pl, e, "template spectra");
+  pl->templates_ready = true;
+  return FDAS_OK;
+}
+
+}  // extern "C"
+
+// Validates a batch and uploads its descriptors when it differs from the last one.
+static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64_t* lengths, int32_t n) {
+  if (!lengths || n <= 0) return pl->fail(FDAS_ERR_ARG, "need n_series > 0 and a lengths array");
+  if (n > pl->max_series) return pl->fail(FDAS_ERR_ARG, "more series than max_batch_samples allows");
+  const int64_t N = pl->p.n_samples;
+  int64_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t len = lengths[i];
+    if (!(len == N || len == N / 2 || len == N / 4) || len < (1 << 17))
+      return pl->fail(FDAS_ERR_ARG, "series lengths must be n_samples, n_samples/2 or n_samples/4 (and >= 2^17)");
+    if (offsets && (offsets[i] < 0 || (offsets[i] & 1)))
+      return pl->fail(FDAS_ERR_ARG, "series offsets must be even and non-negative");
+    tot += len;
+  }
+  if (tot > pl->max_batch) return pl->fail(FDAS_ERR_ARG, "sum of lengths exceeds max_batch_samples");
+  std::vector<int64_t> ko(offsets ? offsets : lengths, (offsets ? offsets : lengths) + n), kl(lengths, lengths + n);
+  if (!offsets) std::fill(ko.begin(), ko.end(), -1);
+  if (pl->batch_valid && ko == pl->key_offsets && kl == pl->key_lengths) return FDAS_OK;
+
+  // segments and template groups
+  int64_t nseg_total = 0;
+  for (int i = 0; i < n; ++i) nseg_total += (lengths[i] / 2 + pl->U - 1) / pl->U;
+  int G;
+  if (pl->p.templates_per_tile > 0) {
+    G = (pl->Z + pl->p.templates_per_tile - 1) / pl->p.templates_per_tile;
+  } else {
+    const int64_t units = (int64_t)pl->cu_count * 8;  // concurrently resident tile owners
+    G = (int)std::min<int64_t>(pl->Z, std::max<int64_t>(1, (8 * units + nseg_total - 1) / nseg_total));
+  }
+  pl->G = G;
+  pl->desc.resize(n);
+  int64_t spec = 0, tiles = 0, maxb = 0;
+  for (int i = 0; i < n; ++i) {
+    SeriesDesc& d = pl->desc[i];
+    d.in_off = offsets ? offsets[i] : 0;
+    d.spec_off = spec;
+    d.plane_off = spec * pl->Z;
+    d.nbins = (int32_t)(lengths[i] / 2);
+    d.nseg = (int32_t)((d.nbins + pl->U - 1) / pl->U);
+    d.tile_begin = tiles;
+    tiles += (int64_t)d.nseg * G;
+    spec += d.nbins;
+    maxb = std::max<int64_t>(maxb, d.nbins);
+  }
+  pl->total_bins = spec;
+  pl->n_tiles = tiles;
+  pl->max_bins = maxb;
+  // group series by length for the FFT launches
+  pl->classes.clear();
+  pl->lists.clear();
+  for (int64_t len : {N, N / 2, N / 4}) {
+    LengthClass c;
+    c.nsamp = len;
+    const int lm = log2i(len / 2);
+    c.M1 = 1 << ((lm + 1) / 2);
+    c.M2 = 1 << (lm / 2);
+    c.list_off = (int)pl->lists.size();
+    for (int i = 0; i < n; ++i)
+      if (lengths[i] == len) pl->lists.push_back(i);
+    c.count = (int)pl->lists.size() - c.list_off;
+    if (c.count) pl->classes.push_back(c);
+  }
+  hipError_t e = hipStreamSynchronize(pl->stream);  // staging buffers may still feed a copy
+  if (e != hipSuccess) return hip_fail(pl, e, "stream sync");
+  std::memcpy(pl->h_desc_pinned, pl->desc.data(), n * sizeof(SeriesDesc));
+  std::memcpy(pl->h_lists_pinned, pl->lists.data(), pl->lists.size() * sizeof(int32_t));
+  e = hipMemcpyAsync(pl->ws + pl->off_desc, pl->h_desc_pinned, n * sizeof(SeriesDesc), hipMemcpyHostToDevice, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "descriptor upload");
+  e = hipMemcpyAsync(pl->ws + pl->off_lists, pl->h_lists_pinned, pl->lists.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "descriptor upload");
+  pl->key_offsets = ko;
+  pl->key_lengths = kl;
+  pl->batch_valid = true;
+  return FDAS_OK;
+}
+
+// Batches that only need the per-series lengths (plane and spectrum layout)
+// reuse the current descriptors when the lengths match.
+static fdas_status ensure_lengths(fdas_plan_t pl, const int64_t* lengths, int32_t n) {
+  if (lengths && n > 0 && pl->batch_valid && pl->key_lengths.size() == (size_t)n &&
+      std::equal(pl->key_lengths.begin(), pl->key_lengths.end(), lengths))
+    return FDAS_OK;
+  return set_batch(pl, nullptr, lengths, n);
+}
+
+static fdas_status run_spectrum(fdas_plan_t pl, const float* series, void* spec_out) {
+  const SeriesDesc* desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
+  const int32_t* lists = reinterpret_cast<const int32_t*>(pl->ws + pl->off_lists);
+  c32* Y = reinterpret_cast<c32*>(pl->ws + pl->off_Y);
+  c32* Zb = reinterpret_cast<c32*>(pl->ws + pl->off_Zb);
+  int32_t* status = reinterpret_cast<int32_t*>(pl->ws + pl->off_status);
+  hipError_t e;
+  for (const LengthClass& c : pl->classes) {
+    const int32_t* l = lists + c.list_off;
+    if ((e = launch_rfft_columns(c.M1, c.M2, series, desc, l, c.count, Y, pl->tw(c.M1), pl->stream)) != hipSuccess)
+      return hip_fail(pl, e, "rfft columns");
+    if ((e = launch_rfft_rows(c.M1, c.M2, desc, l, c.count, Y, Zb, pl->tw(c.M2), pl->stream)) != hipSuccess)
+      return hip_fail(pl, e, "rfft rows");
+    const int M = (int)(c.nsamp / 2);
+    double vs = 1.0;
+    if (pl->p.norm == FDAS_NORM_VARIANCE) vs = 1.0 / std::sqrt((double)c.nsamp * pl->p.noise_var);
+    if ((e = launch_unpack_normalise(pl->p.store_dtype, M, pl->p.norm_block, pl->p.norm, vs, desc, l, c.count, Zb,
+                                     spec_out, status, pl->stream)) != hipSuccess)
+      return hip_fail(pl, e, "unpack/normalise");
+  }
+  return FDAS_OK;
+}
+
+static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64_t plane_bytes) {
+  if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
+  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
+  if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  ConvArgs a;
+  a.spec = spec;
+  a.tspec = pl->ws + pl->off_tspec;
+  a.plane = plane;
+  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
+  a.tw = pl->tw(pl->L);
+  a.n_tiles = pl->n_tiles;
+  a.n_series = (int)pl->desc.size();
+  a.Z = pl->Z;
+  a.G = pl->G;
+  a.U = pl->U;
+  a.hmax = pl->hmax;
+  // The grid is exactly what is resident at once: tiles are dealt
+  // round-robin, so a block that had to wait for a slot would finish last.
+  const int per_block = conv_waves_per_block(pl->L);
+  const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
+  const int64_t blocks_needed = pl->L <= 2048 ? (pl->n_tiles + per_block - 1) / per_block : pl->n_tiles;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)pl->cu_count * per_cu));
+  hipError_t e = launch_conv(pl->L, pl->p.store_dtype, pl->p.plane_dtype, a, grid, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "convolve");
+  return FDAS_OK;
+}
+
+extern "C" {
+
+fdas_status fdas_spectrum(fdas_plan_t pl, const float* series, const int64_t* offsets, const int64_t* lengths,
+                          int32_t n, void* spec_out) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!series || !offsets || !spec_out) return pl->fail(FDAS_ERR_ARG, "series, offsets and spectrum_out are required");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = set_batch(pl, offsets, lengths, n);
+  if (s != FDAS_OK) return s;
+  return run_spectrum(pl, series, spec_out);
+}
+
+fdas_status fdas_convolve_spectrum(fdas_plan_t pl, const void* spectrum, const int64_t* lengths, int32_t n,
+                                   void* plane, int64_t plane_bytes) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!spectrum) return pl->fail(FDAS_ERR_ARG, "spectrum is required");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = ensure_lengths(pl, lengths, n);
+  if (s != FDAS_OK) return s;
+  return run_conv(pl, spectrum, plane, plane_bytes);
+}
+
+fdas_status fdas_convolve(fdas_plan_t pl, const float* series, const int64_t* offsets, const int64_t* lengths,
+                          int32_t n, void* spec_out, void* plane, int64_t plane_bytes) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!series || !offsets) return pl->fail(FDAS_ERR_ARG, "series and offsets are required");
+  if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = set_batch(pl, offsets, lengths, n);
+  if (s != FDAS_OK) return s;
+  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
+  if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
+  if ((s = run_spectrum(pl, series, spec)) != FDAS_OK) return s;
+  return run_conv(pl, spec, plane, plane_bytes);
+}
+
+fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* lengths, int32_t n,
+                              fdas_candidate* cands, int64_t capacity, int64_t* d_count) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!plane || !d_count || capacity < 0 || (capacity > 0 && !cands))
+    return pl->fail(FDAS_ERR_ARG, "plane and d_count are required; cands when capacity > 0");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = ensure_lengths(pl, lengths, n);
+  if (s != FDAS_OK) return s;
+  HarmArgs a;
+  a.plane = plane;
+  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
+  a.cands = cands;
+  a.count = reinterpret_cast<unsigned long long*>(d_count);
+  a.capacity = capacity;
+  for (int i = 0; i < 5; ++i) a.tau[i] = i < pl->nstages ? (float)pl->tau[i] : 0.f;
+  a.z_min = pl->p.z_min;
+  a.z_step = pl->p.z_step;
+  a.n_series = n;
+  a.Z = pl->Z;
+  a.j0 = pl->j0;
+  a.n_harm = pl->p.n_harmonics;
+  a.r_lo = pl->p.r_lo;
+  a.hmax = pl->hmax;
+  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
+    return hip_fail(pl, e, "harmonic sum");
+  return FDAS_OK;
+}
+
+fdas_status fdas_check(fdas_plan_t pl, const int64_t* d_count, int64_t capacity) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "stream sync");
+  int32_t st = 0;
+  e = hipMemcpy(&st, pl->ws + pl->off_status, sizeof(st), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(pl, e, "status read");
+  int64_t cnt = 0;
+  if (d_count) {
+    e = hipMemcpy(&cnt, d_count, sizeof(cnt), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(pl, e, "count read");
+  }
+  if (st) {
+    int32_t zero = 0;
+    e = hipMemcpy(pl->ws + pl->off_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(pl, e, "status clear");
+  }
+  if (st & 1) return pl->fail(FDAS_ERR_NONFINITE, "a spectrum contained NaN or Inf");
+  if (d_count && cnt > capacity)
+    return pl->fail(FDAS_ERR_OVERFLOW, "candidate buffer overflow: " + std::to_string(cnt) + " passing cells, capacity " +
+                                           std::to_string(capacity));
+  return FDAS_OK;
+}
+
+fdas_status fdas_copy_templates(fdas_plan_t pl, void* taps_out, void* spectra_out) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  if (taps_out &&
+      (e = hipMemcpyAsync(taps_out, pl->ws + pl->off_taps, (size_t)pl->Z * pl->K * 16, hipMemcpyDeviceToDevice,
+                          pl->stream)) != hipSuccess)
+    return hip_fail(pl, e, "copy taps");
+  if (spectra_out &&
+      (e = hipMemcpyAsync(spectra_out, pl->ws + pl->off_tspec, (size_t)pl->Z * pl->L * cbytes(pl->p.store_dtype),
+                          hipMemcpyDeviceToDevice, pl->stream)) != hipSuccess)
+    return hip_fail(pl, e, "copy spectra");
+  return FDAS_OK;
+}
+
+fdas_status fdas_copy_thresholds(fdas_plan_t pl, double* tau) {
+  if (!pl || !tau) return FDAS_ERR_ARG;
+  for (int i = 0; i < pl->nstages; ++i) tau[i] = pl->tau[i];
+  return FDAS_OK;
+}
+
+fdas_status fdas_test_fft(fdas_plan_t pl, int32_t L, int32_t direction, const void* in, void* out, int64_t batch) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!in || !out || batch <= 0 || !(direction == -1 || direction == 1))
+    return pl->fail(FDAS_ERR_ARG, "in/out required, batch > 0, direction -1 or +1");
+  if (!pl->tw(L)) return pl->fail(FDAS_ERR_UNSUPPORTED, "FFT length not built");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  e = launch_test_fft(L, direction, (const c32*)in, (c32*)out, batch, pl->tw(L), pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "test fft");
+  return FDAS_OK;
+}
+
+fdas_status fdas_plan_destroy(fdas_plan_t pl) {
+  if (!pl) return FDAS_OK;
+  if (pl->h_desc_pinned || pl->h_lists_pinned) {
+    hipSetDevice(pl->device);
+    hipStreamSynchronize(pl->stream);
+    if (pl->h_desc_pinned) hipHostFree(pl->h_desc_pinned);
+    if (pl->h_lists_pinned) hipHostFree(pl->h_lists_pinned);
+  }
+  delete pl;
+  return FDAS_OK;
+}
+
+const char* fdas_last_error(fdas_plan_t pl) {
+  if (!pl) return g_plan_error.c_str();
+  return pl->err.c_str();
+}
+
+}  // extern "C"

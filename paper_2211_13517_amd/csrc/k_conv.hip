@@ -1,0 +1,200 @@
+// Rows a4-a8: overlap-save correlation with every template and the power plane,
+// fused in one kernel so that the complex products never leave the chip.
+//
+// Work unit ("tile"): one segment of one series and one group of templates.
+// Segment s of a series covers spectrum bins [s U - h_max, s U - h_max + L)
+// (zero outside [0, N/2)).  The tile loads it once, runs the forward FFT and
+// keeps the result F in registers; then, for each template j of its group,
+// multiplies F by the template spectrum T_j (read from L2, it is shared by
+// every tile), runs the inverse FFT and stores |y|^2 of the U = L - 2 h_max
+// outputs free of wrap-around, at plane[j][s U + i].
+//
+// L <= 2048: one wavefront owns a tile and exchanges through its private LDS
+// buffer, so the eight wavefronts of a block never wait for each other.
+// L = 4096, 8192: a block of L/32 threads owns a tile and synchronises.
+// Tiles are dealt round-robin to wavefronts (resp. blocks) of a grid sized to
+// the machine, so every unit runs the same number of tiles to within one.
+#include "fft.hpp"
+#include "launch.hpp"
+
+namespace fdas {
+
+__device__ __forceinline__ int find_series(const SeriesDesc* __restrict__ desc, int n, int64_t tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class FS, int SDT, int PDT, bool BLOCK>
+__device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* xb, const c32* tw, int tid) {
+  using SS = Store<SDT>;
+  using PS = Store<PDT>;
+  using CT = typename SS::cplx_t;
+  using RT = typename PS::real_t;
+  constexpr int P = FS::P, NT = FS::NT, L = FS::L;
+  const int s = find_series(a.desc, a.n_series, tile);
+  const SeriesDesc d = a.desc[s];
+  const int64_t local = tile - d.tile_begin;
+  const int seg = (int)(local / a.G), grp = (int)(local % a.G);
+  const int t0 = (int)(((int64_t)grp * a.Z) / a.G), t1 = (int)(((int64_t)(grp + 1) * a.Z) / a.G);
+  const int r0 = seg * a.U - a.hmax;  // bin of FFT index 0 (segment start, may be negative)
+  const CT* sp = reinterpret_cast<const CT*>(a.spec) + d.spec_off;
+
+  // Segment load: indices outside [0, nbins) read a clamped address and are zeroed.
+  c32 F[P];
+  static_for<0, P>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    const int idx = r0 + tid + NT * c;
+    const int ci = min(max(idx, 0), d.nbins - 1);
+    const c32 val = SS::unpack(sp[ci]);
+    const bool in = (idx >= 0) && (idx < d.nbins);
+    F[c] = {in ? val.re : 0.f, in ? val.im : 0.f};
+  });
+  fft_run<FS, -1, BLOCK>(F, xb, tw, tid);
+
+  const CT* T = reinterpret_cast<const CT*>(a.tspec);
+  RT* out = reinterpret_cast<RT*>(a.plane) + d.plane_off;
+  // Output index i maps to bin r0 + i; valid for i in [lo, hi).
+  const int lo = a.hmax, hi = min(a.hmax + a.U, d.nbins - r0);
+  const uint32_t toff = (uint32_t)tid * sizeof(CT);
+  CT tc[P];
+  static_for<0, P>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    tc[c] = ld_off<CT>(T + (size_t)t0 * L, toff + c * NT * sizeof(CT));
+  });
+  for (int t = t0; t < t1; ++t) {
+    // prefetch the next template while this one is transformed
+    const CT* Tn = T + (size_t)min(t + 1, t1 - 1) * L;
+    CT tn[P];
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      tn[c] = ld_off<CT>(Tn, toff + c * NT * sizeof(CT));
+    });
+    c32 v[P];
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      v[c] = cmul(F[c], SS::unpack(tc[c]));
+    });
+    fft_run<FS, 1, BLOCK>(v, xb, tw, tid);
+    RT* row = out + (size_t)t * (uint32_t)d.nbins;
+    const uint32_t ooff = (uint32_t)(r0 + tid) * sizeof(RT);
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      // the register is out of range for every thread: skip (uniform branch)
+      if (NT * c + NT - 1 < lo || NT * c >= hi) return;
+      const int i = tid + NT * c;
+      if (i >= lo && i < hi) st_off<RT>(row, ooff + c * NT * sizeof(RT), PS::pack_real(cnorm(v[c])));
+    });
+    static_for<0, P>([&](auto cc) { tc[decltype(cc)::value] = tn[decltype(cc)::value]; });
+  }
+}
+
+constexpr int kConvWaves = 8;
+
+template <int L, int SDT, int PDT>
+__global__ __launch_bounds__(512) void k_conv_wave(ConvArgs a) {
+  using FS = typename ShapeOf<L>::type;
+  __shared__ c32 tw[FS::TW_SIZE];
+  __shared__ c32 xb[kConvWaves][FS::XBUF];
+  stage_table(tw, a.tw, FS::TW_SIZE);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * kConvWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kConvWaves + wave; tile < a.n_tiles; tile += nw)
+    conv_tile<FS, SDT, PDT, false>(a, tile, xb[wave], tw, lane);
+}
+
+template <int L, int SDT, int PDT>
+__global__ __launch_bounds__(L / 32) void k_conv_block(ConvArgs a) {
+  using FS = typename ShapeOf<L>::type;
+  __shared__ c32 tw[FS::TW_SIZE];
+  __shared__ c32 xb[FS::XBUF];
+  stage_table(tw, a.tw, FS::TW_SIZE);
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
+    conv_tile<FS, SDT, PDT, true>(a, tile, xb, tw, threadIdx.x);
+}
+
+int conv_waves_per_block(int L) { return L <= 2048 ? kConvWaves : L / 32 / 64; }
+
+template <int L, int SDT, int PDT>
+static void conv_launch(const ConvArgs& a, int grid, hipStream_t st) {
+  if constexpr (L <= 2048)
+    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT>), dim3(grid), dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_conv_block<L, SDT, PDT>), dim3(grid), dim3(L / 32), 0, st, a);
+}
+
+template <int L, int SDT, int PDT>
+static int occ() {
+  int n = 0;
+  if constexpr (L <= 2048)
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT>, 512, 0);
+  else
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT>, L / 32, 0);
+  return n;
+}
+
+template <int L>
+static int occ_l(int sdt, int pdt) {
+  auto sel = [&](auto sd) -> int {
+    constexpr int S = decltype(sd)::value;
+    switch (pdt) {
+      case FDAS_F32: return occ<L, S, FDAS_F32>();
+      case FDAS_BF16: return occ<L, S, FDAS_BF16>();
+      default: return occ<L, S, FDAS_F16>();
+    }
+  };
+  switch (sdt) {
+    case FDAS_F32: return sel(std::integral_constant<int, FDAS_F32>{});
+    case FDAS_BF16: return sel(std::integral_constant<int, FDAS_BF16>{});
+    default: return sel(std::integral_constant<int, FDAS_F16>{});
+  }
+}
+
+int conv_blocks_per_cu(int L, int sdt, int pdt) {
+  switch (L) {
+    case 1024: return occ_l<1024>(sdt, pdt);
+    case 2048: return occ_l<2048>(sdt, pdt);
+    case 4096: return occ_l<4096>(sdt, pdt);
+    case 8192: return occ_l<8192>(sdt, pdt);
+    default: return 1;
+  }
+}
+
+template <int L, int SDT>
+static hipError_t conv_pdt(int pdt, const ConvArgs& a, int grid, hipStream_t st) {
+  switch (pdt) {
+    case FDAS_F32: conv_launch<L, SDT, FDAS_F32>(a, grid, st); break;
+    case FDAS_BF16: conv_launch<L, SDT, FDAS_BF16>(a, grid, st); break;
+    case FDAS_F16: conv_launch<L, SDT, FDAS_F16>(a, grid, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t conv_sdt(int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st) {
+  switch (sdt) {
+    case FDAS_F32: return conv_pdt<L, FDAS_F32>(pdt, a, grid, st);
+    case FDAS_BF16: return conv_pdt<L, FDAS_BF16>(pdt, a, grid, st);
+    case FDAS_F16: return conv_pdt<L, FDAS_F16>(pdt, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_conv(int L, int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st) {
+  switch (L) {
+    case 1024: return conv_sdt<1024>(sdt, pdt, a, grid, st);
+    case 2048: return conv_sdt<2048>(sdt, pdt, a, grid, st);
+    case 4096: return conv_sdt<4096>(sdt, pdt, a, grid, st);
+    case 8192: return conv_sdt<8192>(sdt, pdt, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fdas

@@ -1,0 +1,89 @@
+// Host-side launchers of the FDAS kernels (one definition per kernel file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "fresnel.hpp"
+
+namespace fdas {
+
+// One series of a batch, as the kernels see it.
+struct SeriesDesc {
+  int64_t in_off;      // first float32 sample in the input
+  int64_t spec_off;    // first complex bin in the packed spectrum (and FFT scratch)
+  int64_t plane_off;   // first element of the series' power plane (= Z * spec_off)
+  int64_t tile_begin;  // first convolution tile of the series
+  int32_t nbins;       // N/2
+  int32_t nseg;        // overlap-save segments ceil(nbins / U)
+};
+
+// Twiddle tables of the FFT sizes the library builds, concatenated; offsets
+// are in complex entries.
+struct TwiddleSet {
+  int off[14];  // indexed by log2(L)
+};
+int twiddle_table_size(int L);             // entries, 0 if the size is not built
+void twiddle_table_fill(int L, c32* dst);  // forward-sign twiddles of FftShape<L, P(L)>
+int fft_points_per_thread(int L);
+
+}  // namespace fdas
+#include "fft.hpp"
+namespace fdas {
+// FFT shapes the library builds: L points, P per thread, pass radix R.
+template <int L> struct ShapeOf;
+template <> struct ShapeOf<256> { using type = FftShape<256, 4, 4>; };
+template <> struct ShapeOf<512> { using type = FftShape<512, 8, 8>; };
+template <> struct ShapeOf<1024> { using type = FftShape<1024, 16, 16>; };
+template <> struct ShapeOf<2048> { using type = FftShape<2048, 32, 16>; };
+template <> struct ShapeOf<4096> { using type = FftShape<4096, 32, 32>; };
+template <> struct ShapeOf<8192> { using type = FftShape<8192, 32, 32>; };
+
+// a1-a2
+hipError_t launch_rfft_columns(int M1, int M2, const float* x, const SeriesDesc* desc, const int32_t* list,
+                               int nlist, c32* Y, const c32* tw, hipStream_t st);
+hipError_t launch_rfft_rows(int M1, int M2, const SeriesDesc* desc, const int32_t* list, int nlist,
+                            const c32* Y, c32* Zb, const c32* tw, hipStream_t st);
+hipError_t launch_unpack_normalise(int sdt, int M, int B, int mode, double var_scale, const SeriesDesc* desc,
+                                   const int32_t* list, int nlist, const c32* Zb, void* spec, int32_t* status,
+                                   hipStream_t st);
+
+// a3
+hipError_t launch_exp_table(int L, c64* tab, hipStream_t st);
+hipError_t launch_template_taps(double z_min, double z_step, int Z, int margin, int hmax, c64* taps,
+                                hipStream_t st);
+hipError_t launch_template_spectra(int sdt, const c64* taps, const c64* tab, int Z, int hmax, int L, void* out,
+                                   hipStream_t st);
+
+// a4-a8
+struct ConvArgs {
+  const void* spec;        // packed normalised spectrum, store dtype
+  const void* tspec;       // template spectra [Z][L], store dtype
+  void* plane;             // packed planes, plane dtype
+  const SeriesDesc* desc;  // per series
+  const c32* tw;           // twiddle table of size L
+  int64_t n_tiles;         // sum over series of nseg * G
+  int32_t n_series, Z, G, U, hmax;
+};
+hipError_t launch_conv(int L, int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st);
+int conv_waves_per_block(int L);
+int conv_blocks_per_cu(int L, int sdt, int pdt);  // resident blocks per CU (occupancy query)
+
+// a9-a10
+struct HarmArgs {
+  const void* plane;
+  const SeriesDesc* desc;
+  fdas_candidate* cands;
+  unsigned long long* count;
+  int64_t capacity;
+  float tau[5];
+  double z_min, z_step;
+  int32_t n_series, Z, j0, n_harm, r_lo, hmax;
+};
+hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
+
+// self-test hook: batched complex FFT of size L
+hipError_t launch_test_fft(int L, int dir, const c32* in, c32* out, int64_t batch, const c32* tw, hipStream_t st);
+
+}  // namespace fdas
