@@ -308,7 +308,9 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
   if (pl->p.templates_per_tile > 0) {
     G = (pl->Z + pl->p.templates_per_tile - 1) / pl->p.templates_per_tile;
   } else {
-    const int64_t units = (int64_t)pl->cu_count * 8;  // concurrently resident tile owners
+    // concurrently resident tile owners (wavefronts or blocks) on the device
+    const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
+    const int64_t units = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
     G = (int)std::min<int64_t>(pl->Z, std::max<int64_t>(1, (8 * units + nseg_total - 1) / nseg_total));
   }
   pl->G = G;
@@ -411,7 +413,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   // round-robin, so a block that had to wait for a slot would finish last.
   const int per_block = conv_waves_per_block(pl->L);
   const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
-  const int64_t blocks_needed = pl->L <= 2048 ? (pl->n_tiles + per_block - 1) / per_block : pl->n_tiles;
+  const int64_t blocks_needed = pl->L == 1024 ? (pl->n_tiles + per_block - 1) / per_block : pl->n_tiles;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)pl->cu_count * per_cu));
   hipError_t e = launch_conv(pl->L, pl->p.store_dtype, pl->p.plane_dtype, a, grid, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "convolve");

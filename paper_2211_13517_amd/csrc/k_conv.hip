@@ -93,11 +93,20 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
   }
 }
 
-constexpr int kConvWaves = 8;
+constexpr int kConvWaves = 4;  // wavefronts per block of the one-wavefront-per-FFT kernel
 
+// Convolution FFT shapes: 16 points per thread, radix 16 (the twiddle table
+// depends only on the radix sequence, so it is the one of ShapeOf<L>).
+template <int L>
+using ConvShape = FftShape<L, 16, 16>;
+
+// 16-bit storage leaves room for three wavefronts per SIMD; FP32 storage (twice
+// the template registers) runs two.
 template <int L, int SDT, int PDT>
-__global__ __launch_bounds__(512) void k_conv_wave(ConvArgs a) {
-  using FS = typename ShapeOf<L>::type;
+__global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(SDT == FDAS_F32 ? 2 : 3)))
+void k_conv_wave(ConvArgs a) {
+  using FS = ConvShape<L>;
+  static_assert(FS::NT == 64, "one wavefront per FFT");
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[kConvWaves][FS::XBUF];
   stage_table(tw, a.tw, FS::TW_SIZE);
@@ -109,8 +118,8 @@ __global__ __launch_bounds__(512) void k_conv_wave(ConvArgs a) {
 }
 
 template <int L, int SDT, int PDT>
-__global__ __launch_bounds__(L / 32) void k_conv_block(ConvArgs a) {
-  using FS = typename ShapeOf<L>::type;
+__global__ __launch_bounds__(ConvShape<L>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_block(ConvArgs a) {
+  using FS = ConvShape<L>;
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[FS::XBUF];
   stage_table(tw, a.tw, FS::TW_SIZE);
@@ -119,23 +128,25 @@ __global__ __launch_bounds__(L / 32) void k_conv_block(ConvArgs a) {
     conv_tile<FS, SDT, PDT, true>(a, tile, xb, tw, threadIdx.x);
 }
 
-int conv_waves_per_block(int L) { return L <= 2048 ? kConvWaves : L / 32 / 64; }
+int conv_waves_per_block(int L) { return L == 1024 ? kConvWaves : L / 16 / 64; }
 
 template <int L, int SDT, int PDT>
 static void conv_launch(const ConvArgs& a, int grid, hipStream_t st) {
-  if constexpr (L <= 2048)
-    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT>), dim3(grid), dim3(512), 0, st, a);
+  if constexpr (ConvShape<L>::NT == 64)
+    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT>), dim3(grid), dim3(64 * kConvWaves), 0, st, a);
   else
-    hipLaunchKernelGGL((k_conv_block<L, SDT, PDT>), dim3(grid), dim3(L / 32), 0, st, a);
+    hipLaunchKernelGGL((k_conv_block<L, SDT, PDT>), dim3(grid), dim3(ConvShape<L>::NT), 0, st, a);
 }
 
 template <int L, int SDT, int PDT>
 static int occ() {
   int n = 0;
-  if constexpr (L <= 2048)
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT>, 512, 0);
+  hipError_t e;
+  if constexpr (ConvShape<L>::NT == 64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT>, 64 * kConvWaves, 0);
   else
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT>, L / 32, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT>, ConvShape<L>::NT, 0);
+  if (e != hipSuccess) n = 1;
   return n;
 }
 

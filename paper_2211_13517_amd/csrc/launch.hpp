@@ -37,8 +37,8 @@ template <> struct ShapeOf<256> { using type = FftShape<256, 4, 4>; };
 template <> struct ShapeOf<512> { using type = FftShape<512, 8, 8>; };
 template <> struct ShapeOf<1024> { using type = FftShape<1024, 16, 16>; };
 template <> struct ShapeOf<2048> { using type = FftShape<2048, 32, 16>; };
-template <> struct ShapeOf<4096> { using type = FftShape<4096, 32, 32>; };
-template <> struct ShapeOf<8192> { using type = FftShape<8192, 32, 32>; };
+template <> struct ShapeOf<4096> { using type = FftShape<4096, 16, 16>; };
+template <> struct ShapeOf<8192> { using type = FftShape<8192, 16, 16>; };
 
 // a1-a2
 hipError_t launch_rfft_columns(int M1, int M2, const float* x, const SeriesDesc* desc, const int32_t* list,
