@@ -164,6 +164,59 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);
 
+/* Row a12, forward: Fourier-interpolated matched-filter power at off-grid
+ * candidates (section 2.1's matched filter evaluated between grid points):
+ *   y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),
+ *   w = kernel_margin + ceil(|z|/2) (32 bins at z = 0), A_k = 0 outside [0, n_bins),
+ *   P = |y|^2, evaluated in FP64 and returned as float p[i].
+ * spectrum: store_dtype complex [n_bins] (one series, e.g. from fdas_spectrum);
+ * r, z, p: float [n] device arrays; y_out (optional, complex128 [n]) keeps y for
+ * the adjoint.  n_bins <= max_batch_samples / 2. */
+fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const float *r, const float *z,
+                          int64_t n, float *p, void *y_out);
+
+/* Row a12, adjoint: given the upstream gradient grad_p[i] of a real loss with
+ * respect to p[i], writes grad_r[i] = grad_p 2 Re(conj(y) dy/dr),
+ * grad_z[i] = grad_p 2 Re(conj(y) dy/dz) (dy/dr = -sum A_k conj(d rho/dq),
+ * dy/dz = sum A_k conj(d rho/dz), FP64), and, if grad_spectrum is non-NULL,
+ * overwrites it (complex64 [n_bins]) with sum_i grad_p[i] 2 y_i rho(k - r_i, z_i),
+ * the gradient with respect to A_k as d/dRe + i d/dIm.  That sum is formed in
+ * 2^-40 fixed point with integer atomics, so it is bitwise deterministic.
+ * y: the forward's y_out, or NULL to recompute it.  Uses the workspace. */
+fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const float *r,
+                               const float *z, const void *y, const float *grad_p, int64_t n, float *grad_r,
+                               float *grad_z, void *grad_spectrum);
+
+/* Row a12, refinement: n_iter steps of preconditioned gradient ascent of
+ * P(r, z) per candidate (step (dP/dr / (2 a P), dP/dz / (2 b P)) with
+ * a = pi^2/3, b = pi^2/180, clamped to 0.25 bin and 2 z, halved until P
+ * grows), r and z updated in place (float [n]), and the final power evaluated
+ * in FP64 at the returned position into p_final (double [n]). */
+fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, float *r, float *z, int64_t n,
+                        int32_t n_iter, double *p_final);
+
+/* Rows a1-a10 for one batch in one call: resets *d_count (with a kernel),
+ * then spectrum, convolution and harmonic sums exactly as fdas_spectrum,
+ * fdas_convolve_spectrum and fdas_harmonic_sum.  With use_graph != 0 the
+ * launches are captured once into a HIP graph (the plan's stream must not be
+ * the default stream) and replayed on later calls with the same pointers,
+ * offsets and lengths; the batch descriptors are uploaded before capture.
+ * Row a11: the batch may mix full-length and decimated series; the
+ * convolution tiles of all series go to one persistent launch. */
+fdas_status fdas_search(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
+                        const int64_t *lengths_host, int32_t n_series, void *spectrum_out, void *plane_out,
+                        int64_t plane_bytes, fdas_candidate *cands, int64_t capacity, int64_t *d_count,
+                        int32_t use_graph);
+
+/* Row a11, tuning: times the convolution of one full-length noise spectrum
+ * for every segment length L in {1024, 2048, 4096, 8192} allowed by the z
+ * range and templates_per_tile in {auto, 12, 24, 48, 96} on `device`/`hip_stream`,
+ * using `scratch` (device memory, at least workspace + spectrum + plane of one
+ * series; FDAS_ERR_NOMEM names the size), and writes the fastest parameters
+ * to *best (and its time in ms to *best_ms).  Blocks until done. */
+fdas_status fdas_autotune(const fdas_params *base, int device, void *hip_stream, void *scratch,
+                          int64_t scratch_bytes, fdas_params *best, double *best_ms);
+
 /* Waits for the plan's stream, then reports device-side conditions latched
  * since the last fdas_check: FDAS_ERR_NONFINITE if a spectrum held NaN/Inf,
  * FDAS_ERR_OVERFLOW if d_count (optional, device) exceeds capacity. Clears

@@ -49,6 +49,7 @@ class Params(ctypes.Structure):
 
 EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace", "fdas_make_templates",
            "fdas_spectrum", "fdas_convolve_spectrum", "fdas_convolve", "fdas_harmonic_sum", "fdas_check",
+           "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
            "fdas_last_error"]
 
@@ -76,6 +77,12 @@ def load(path: str = LIB_PATH):
         "fdas_convolve": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64], c_int),
         "fdas_harmonic_sum": ([P, P, POINTER(c_int64), c_int32, P, c_int64, P], c_int),
         "fdas_check": ([P, P, c_int64], c_int),
+        "fdas_rz_power": ([P, P, c_int64, P, P, c_int64, P, P], c_int),
+        "fdas_rz_power_grad": ([P, P, c_int64, P, P, P, P, c_int64, P, P, P], c_int),
+        "fdas_refine": ([P, P, c_int64, P, P, c_int64, c_int32, P], c_int),
+        "fdas_search": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64, P, c_int64, P, c_int32],
+                        c_int),
+        "fdas_autotune": ([POINTER(Params), c_int, P, P, c_int64, POINTER(Params), POINTER(c_double)], c_int),
         "fdas_copy_templates": ([P, P, P], c_int),
         "fdas_copy_thresholds": ([P, POINTER(c_double)], c_int),
         "fdas_test_fft": ([P, c_int32, c_int32, P, P, c_int64], c_int),
@@ -116,20 +123,23 @@ class Plan:
     """
 
     def __init__(self, device: int = 0, store: str = "f32", plane: str = "f32", norm: str = "median",
-                 make_templates: bool = True, **kw):
+                 make_templates: bool = True, stream=None, params: Optional[Params] = None, **kw):
         import torch
         self.lib = load()
         p = Params()
-        self._check(self.lib.fdas_default_params(byref(p)), None)
-        p.store_dtype = DTYPES[store]
-        p.plane_dtype = DTYPES[plane]
-        p.norm = NORMS[norm]
+        if params is not None:
+            ctypes.memmove(byref(p), byref(params), ctypes.sizeof(Params))
+        else:
+            self._check(self.lib.fdas_default_params(byref(p)), None)
+            p.store_dtype = DTYPES[store]
+            p.plane_dtype = DTYPES[plane]
+            p.norm = NORMS[norm]
         for k, v in kw.items():
             if not hasattr(p, k):
                 raise TypeError(f"unknown parameter {k}")
             setattr(p, k, v)
         self.device = torch.device("cuda", device)
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = c_void_p()
         st = self.lib.fdas_plan(byref(p), device, c_void_p(self.stream.cuda_stream), byref(h))
         if st != 0:
@@ -231,9 +241,62 @@ class Plan:
                                                c_void_p(cands.data_ptr()), capacity, c_void_p(count.data_ptr())))
         return cands, count
 
+    def search(self, series, offsets: Sequence[int], lengths: Sequence[int], plane, cands, count,
+               spectrum=None, use_graph: bool = False):
+        """Rows a1-a10 for one batch (optionally through a captured HIP graph)."""
+        nbytes = plane.numel() * plane.element_size()
+        self._check(self.lib.fdas_search(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
+                                         len(lengths), None if spectrum is None else c_void_p(spectrum.data_ptr()),
+                                         c_void_p(plane.data_ptr()), nbytes, c_void_p(cands.data_ptr()),
+                                         cands.shape[0], c_void_p(count.data_ptr()), 1 if use_graph else 0))
+
     def check(self, count=None, capacity: int = 0):
         """Synchronises and raises FdasError for latched device conditions."""
         self._check(self.lib.fdas_check(self.handle, None if count is None else c_void_p(count.data_ptr()), capacity))
+
+    # ------------------------------------------------------------ refinement
+    def rz_power(self, spectrum, r, z, keep_y: bool = True):
+        """P(r, z) (float32 [n]) and y (complex128 [n]) at off-grid candidates."""
+        import torch
+        r = r.contiguous().float()
+        z = z.contiguous().float()
+        n = r.numel()
+        p = torch.empty(n, dtype=torch.float32, device=self.device)
+        y = torch.empty(n, dtype=torch.complex128, device=self.device) if keep_y else None
+        nb = spectrum.shape[0]
+        self._check(self.lib.fdas_rz_power(self.handle, c_void_p(spectrum.data_ptr()), nb, c_void_p(r.data_ptr()),
+                                           c_void_p(z.data_ptr()), n, c_void_p(p.data_ptr()),
+                                           None if y is None else c_void_p(y.data_ptr())))
+        return p, y
+
+    def rz_power_grad(self, spectrum, r, z, grad_p, y=None, want_spectrum: bool = True):
+        """(grad_r, grad_z, grad_spectrum complex64 [n_bins] or None) for upstream grad_p."""
+        import torch
+        r = r.contiguous().float()
+        z = z.contiguous().float()
+        gp = grad_p.contiguous().float()
+        n = r.numel()
+        gr = torch.empty(n, dtype=torch.float32, device=self.device)
+        gz = torch.empty(n, dtype=torch.float32, device=self.device)
+        nb = spectrum.shape[0]
+        gs = torch.empty(nb, dtype=torch.complex64, device=self.device) if want_spectrum else None
+        self._check(self.lib.fdas_rz_power_grad(
+            self.handle, c_void_p(spectrum.data_ptr()), nb, c_void_p(r.data_ptr()), c_void_p(z.data_ptr()),
+            None if y is None else c_void_p(y.data_ptr()), c_void_p(gp.data_ptr()), n, c_void_p(gr.data_ptr()),
+            c_void_p(gz.data_ptr()), None if gs is None else c_void_p(gs.data_ptr())))
+        return gr, gz, gs
+
+    def refine(self, spectrum, r, z, n_iter: int = 30):
+        """Gradient-ascent refinement: returns (r, z, p_final float64)."""
+        import torch
+        r = r.clone().contiguous().float()
+        z = z.clone().contiguous().float()
+        n = r.numel()
+        pf = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._check(self.lib.fdas_refine(self.handle, c_void_p(spectrum.data_ptr()), spectrum.shape[0],
+                                         c_void_p(r.data_ptr()), c_void_p(z.data_ptr()), n, n_iter,
+                                         c_void_p(pf.data_ptr())))
+        return r, z, pf
 
     def test_fft(self, x, direction: int):
         """Batched complex FFT of length L through the library's FFT engine (self-test)."""
@@ -244,6 +307,90 @@ class Plan:
         self._check(self.lib.fdas_test_fft(self.handle, L, direction, c_void_p(x.data_ptr()),
                                            c_void_p(out.data_ptr()), x.numel() // L))
         return out
+
+
+def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) -> Params:
+    """Fastest (segment_len, templates_per_tile) for the given parameters, measured
+    by fdas_autotune on this GPU; cached as JSON keyed by device and shape."""
+    import json
+    import torch
+    lib = load()
+    p = Params()
+    lib.fdas_default_params(byref(p))
+    for k, v in kw.items():
+        if k in ("store", "plane"):
+            setattr(p, k + "_dtype", DTYPES[v])
+        elif k == "norm":
+            p.norm = NORMS[v]
+        else:
+            setattr(p, k, v)
+    name = torch.cuda.get_device_properties(device).gcnArchName if torch.cuda.is_available() else "none"
+    key = f"{name}|N={p.n_samples}|z={p.z_min},{p.z_max},{p.z_step}|m={p.kernel_margin}|s={p.store_dtype}|p={p.plane_dtype}"
+    cache = cache or os.environ.get("FDAS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fdas_tune.json"))
+    table = {}
+    if os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        p.segment_len, p.templates_per_tile = table[key]["segment_len"], table[key]["templates_per_tile"]
+        return p
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    nb = p.n_samples // 2
+    z = int(round((p.z_max - p.z_min) / p.z_step)) + 1
+    need = nb * 8 + nb * z * 4 + nb * 40 + (64 << 20)
+    scratch = torch.empty(need, dtype=torch.uint8, device=f"cuda:{device}")
+    best, ms = Params(), c_double()
+    st_ = lib.fdas_autotune(byref(p), device, c_void_p(st.cuda_stream), c_void_p(scratch.data_ptr()), need,
+                            byref(best), byref(ms))
+    if st_ != 0:
+        raise FdasError(st_, lib.fdas_last_error(None).decode())
+    table[key] = {"segment_len": best.segment_len, "templates_per_tile": best.templates_per_tile, "conv_ms": ms.value}
+    try:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        json.dump(table, open(cache, "w"), indent=1)
+    except OSError:
+        pass
+    return best
+
+
+def _rz_function():
+    import torch
+
+    class RZPower(torch.autograd.Function):
+        """P(r, z) of a plan's spectrum with the library's hand-written adjoint.
+
+        ``spectrum`` is complex64 [n_bins] (FP32 storage plans); gradients flow
+        to it (PyTorch's d/dRe + i d/dIm convention), to r and to z."""
+
+        @staticmethod
+        def forward(ctx, spectrum, r, z, plan):
+            spec = torch.view_as_real(spectrum)
+            p, y = plan.rz_power(spec, r, z)
+            ctx.plan = plan
+            ctx.save_for_backward(spectrum, r, z, y)
+            return p
+
+        @staticmethod
+        def backward(ctx, grad_p):
+            spectrum, r, z, y = ctx.saved_tensors
+            want = ctx.needs_input_grad[0]
+            gr, gz, gs = ctx.plan.rz_power_grad(torch.view_as_real(spectrum), r, z, grad_p, y=y, want_spectrum=want)
+            return gs, gr.to(r.dtype), gz.to(z.dtype), None
+
+    return RZPower
+
+
+_RZ = None
+
+
+def rz_power(spectrum, r, z, plan):
+    """Differentiable P(r, z) (see RZPower)."""
+    global _RZ
+    if _RZ is None:
+        _RZ = _rz_function()
+    return _RZ.apply(spectrum, r, z, plan)
 
 
 CAND_FIELDS = ("series", "harm", "R", "j", "r", "z", "power", "sigma")

@@ -88,6 +88,10 @@ struct fdas_plan_s {
   bool batch_valid = false;
   SeriesDesc* h_desc_pinned = nullptr;
   int32_t* h_lists_pinned = nullptr;
+  // captured a1-a10 graph and the arguments it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uintptr_t> graph_key;
 
   fdas_status fail(fdas_status s, const std::string& m) {
     err = m;
@@ -493,6 +497,172 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
   return FDAS_OK;
 }
 
+}  // extern "C"
+
+// Enqueues a1-a10 for the current batch (descriptors already uploaded).
+static fdas_status enqueue_search(fdas_plan_t pl, const float* series, void* spec, void* plane, int64_t plane_bytes,
+                                  fdas_candidate* cands, int64_t capacity, int64_t* d_count) {
+  hipError_t e = launch_fill_i64(d_count, 1, 0, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "count reset");
+  fdas_status s = run_spectrum(pl, series, spec);
+  if (s != FDAS_OK) return s;
+  if ((s = run_conv(pl, spec, plane, plane_bytes)) != FDAS_OK) return s;
+  HarmArgs a;
+  a.plane = plane;
+  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
+  a.cands = cands;
+  a.count = reinterpret_cast<unsigned long long*>(d_count);
+  a.capacity = capacity;
+  for (int i = 0; i < 5; ++i) a.tau[i] = i < pl->nstages ? (float)pl->tau[i] : 0.f;
+  a.z_min = pl->p.z_min;
+  a.z_step = pl->p.z_step;
+  a.n_series = (int)pl->desc.size();
+  a.Z = pl->Z;
+  a.j0 = pl->j0;
+  a.n_harm = pl->p.n_harmonics;
+  a.r_lo = pl->p.r_lo;
+  a.hmax = pl->hmax;
+  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
+    return hip_fail(pl, e, "harmonic sum");
+  return FDAS_OK;
+}
+
+extern "C" {
+
+fdas_status fdas_search(fdas_plan_t pl, const float* series, const int64_t* offsets, const int64_t* lengths, int32_t n,
+                        void* spec_out, void* plane, int64_t plane_bytes, fdas_candidate* cands, int64_t capacity,
+                        int64_t* d_count, int32_t use_graph) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
+  if (!series || !offsets || !d_count || capacity < 0 || (capacity > 0 && !cands))
+    return pl->fail(FDAS_ERR_ARG, "series, offsets and d_count are required; cands when capacity > 0");
+  if (use_graph && pl->stream == nullptr)
+    return pl->fail(FDAS_ERR_STATE, "graph mode needs a non-default stream");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = set_batch(pl, offsets, lengths, n);  // uploads descriptors outside any capture
+  if (s != FDAS_OK) return s;
+  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
+  if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
+  if (!use_graph) return enqueue_search(pl, series, spec, plane, plane_bytes, cands, capacity, d_count);
+
+  std::vector<uintptr_t> key = {(uintptr_t)series, (uintptr_t)spec, (uintptr_t)plane, (uintptr_t)plane_bytes,
+                                (uintptr_t)cands, (uintptr_t)capacity, (uintptr_t)d_count};
+  for (int i = 0; i < n; ++i) {
+    key.push_back((uintptr_t)offsets[i]);
+    key.push_back((uintptr_t)lengths[i]);
+  }
+  if (!pl->graph_exec || key != pl->graph_key) {
+    if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    pl->graph_exec = nullptr;
+    pl->graph = nullptr;
+    if ((e = hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(pl, e, "begin capture");
+    s = enqueue_search(pl, series, spec, plane, plane_bytes, cands, capacity, d_count);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(pl->stream, &g);
+    if (s != FDAS_OK) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(pl, e, "end capture");
+    if ((e = hipGraphInstantiate(&pl->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      hipGraphDestroy(g);
+      return hip_fail(pl, e, "graph instantiate");
+    }
+    pl->graph = g;
+    pl->graph_key = key;
+  }
+  if ((e = hipGraphLaunch(pl->graph_exec, pl->stream)) != hipSuccess) return hip_fail(pl, e, "graph launch");
+  return FDAS_OK;
+}
+
+fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream, void* scratch, int64_t scratch_bytes,
+                          fdas_params* best, double* best_ms) {
+  if (!base || !best || !scratch) {
+    g_plan_error = "base, best and scratch are required";
+    return FDAS_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int Ls[] = {1024, 2048, 4096, 8192};
+  const int tpts[] = {0, 12, 24, 48, 96};
+  double best_t = 1e300;
+  fdas_params winner = *base;
+  bool any = false;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    g_plan_error = "hipEventCreate failed";
+    return FDAS_ERR_HIP;
+  }
+  fdas_status result = FDAS_OK;
+  for (int L : Ls) {
+    for (int tpt : tpts) {
+      fdas_params p = *base;
+      p.segment_len = L;
+      p.templates_per_tile = tpt;
+      p.max_batch_samples = p.n_samples;
+      fdas_plan_t pl = nullptr;
+      if (fdas_plan(&p, device, hip_stream, &pl) != FDAS_OK) continue;  // e.g. L < 4 h_max
+      if (tpt > pl->Z) {
+        fdas_plan_destroy(pl);
+        continue;
+      }
+      const int64_t nb = p.n_samples / 2;
+      const int64_t spec_bytes = align256(nb * cbytes(p.store_dtype));
+      const int64_t plane_bytes = align256(nb * pl->Z * rbytes(p.plane_dtype));
+      const int64_t need = pl->total + spec_bytes + plane_bytes;
+      if (need > scratch_bytes) {
+        g_plan_error = "autotune scratch too small: need " + std::to_string(need) + " bytes";
+        fdas_plan_destroy(pl);
+        result = FDAS_ERR_NOMEM;
+        break;
+      }
+      char* base_ptr = (char*)scratch;
+      fdas_status s = fdas_set_workspace(pl, base_ptr, pl->total);
+      if (s == FDAS_OK) s = fdas_make_templates(pl);
+      void* spec = base_ptr + pl->total;
+      void* plane = base_ptr + pl->total + spec_bytes;
+      if (s == FDAS_OK && launch_fill_noise(spec, p.store_dtype, nb, 12345u, st) != hipSuccess) s = FDAS_ERR_HIP;
+      const int64_t len = p.n_samples;
+      float best_one = 1e30f;
+      for (int rep = 0; rep < 4 && s == FDAS_OK; ++rep) {
+        hipEventRecord(e0, st);
+        s = fdas_convolve_spectrum(pl, spec, &len, 1, plane, plane_bytes);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) s = FDAS_ERR_HIP;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best_one = std::min(best_one, ms);  // first run warms up
+      }
+      fdas_plan_destroy(pl);
+      if (s != FDAS_OK) {
+        result = s;
+        break;
+      }
+      if (best_one < best_t) {
+        best_t = best_one;
+        winner = p;
+        any = true;
+      }
+    }
+    if (result != FDAS_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (result != FDAS_OK) return result;
+  if (!any) {
+    g_plan_error = "no candidate configuration was valid";
+    return FDAS_ERR_ARG;
+  }
+  winner.max_batch_samples = base->max_batch_samples;
+  *best = winner;
+  if (best_ms) *best_ms = best_t;
+  return FDAS_OK;
+}
+
 fdas_status fdas_check(fdas_plan_t pl, const int64_t* d_count, int64_t capacity) {
   if (!pl) return FDAS_ERR_ARG;
   if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
@@ -541,6 +711,55 @@ fdas_status fdas_copy_thresholds(fdas_plan_t pl, double* tau) {
   return FDAS_OK;
 }
 
+static fdas_status rz_check(fdas_plan_t pl, const void* spec, int64_t nb, int64_t n) {
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!spec || nb <= 0 || n < 0) return pl->fail(FDAS_ERR_ARG, "spectrum, n_bins > 0 and n >= 0 are required");
+  if (nb > pl->max_batch / 2) return pl->fail(FDAS_ERR_ARG, "n_bins exceeds max_batch_samples / 2");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  return FDAS_OK;
+}
+
+fdas_status fdas_rz_power(fdas_plan_t pl, const void* spec, int64_t nb, const float* r, const float* z, int64_t n,
+                          float* p, void* y_out) {
+  if (!pl) return FDAS_ERR_ARG;
+  fdas_status s = rz_check(pl, spec, nb, n);
+  if (s != FDAS_OK) return s;
+  if (n == 0) return FDAS_OK;
+  if (!r || !z || !p) return pl->fail(FDAS_ERR_ARG, "r, z and p are required");
+  hipError_t e = launch_rz_power(pl->p.store_dtype, spec, nb, r, z, n, pl->p.kernel_margin, p, (c64*)y_out, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "rz power");
+  return FDAS_OK;
+}
+
+fdas_status fdas_rz_power_grad(fdas_plan_t pl, const void* spec, int64_t nb, const float* r, const float* z,
+                               const void* y, const float* grad_p, int64_t n, float* grad_r, float* grad_z,
+                               void* grad_spectrum) {
+  if (!pl) return FDAS_ERR_ARG;
+  fdas_status s = rz_check(pl, spec, nb, n);
+  if (s != FDAS_OK) return s;
+  if (n == 0) return FDAS_OK;
+  if (!r || !z || !grad_p || !grad_r || !grad_z) return pl->fail(FDAS_ERR_ARG, "r, z, grad_p, grad_r, grad_z are required");
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(pl->ws + pl->off_Y);
+  hipError_t e = launch_rz_grad(pl->p.store_dtype, spec, nb, r, z, (const c64*)y, grad_p, n, pl->p.kernel_margin, grad_r,
+                                grad_z, (float*)grad_spectrum, acc, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "rz power grad");
+  return FDAS_OK;
+}
+
+fdas_status fdas_refine(fdas_plan_t pl, const void* spec, int64_t nb, float* r, float* z, int64_t n, int32_t n_iter,
+                        double* p_final) {
+  if (!pl) return FDAS_ERR_ARG;
+  fdas_status s = rz_check(pl, spec, nb, n);
+  if (s != FDAS_OK) return s;
+  if (n == 0) return FDAS_OK;
+  if (!r || !z || !p_final || n_iter < 0 || n_iter > 1000)
+    return pl->fail(FDAS_ERR_ARG, "r, z, p_final are required and 0 <= n_iter <= 1000");
+  hipError_t e = launch_refine(pl->p.store_dtype, spec, nb, r, z, n, n_iter, pl->p.kernel_margin, p_final, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "refine");
+  return FDAS_OK;
+}
+
 fdas_status fdas_test_fft(fdas_plan_t pl, int32_t L, int32_t direction, const void* in, void* out, int64_t batch) {
   if (!pl) return FDAS_ERR_ARG;
   if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
@@ -556,6 +775,8 @@ fdas_status fdas_test_fft(fdas_plan_t pl, int32_t L, int32_t direction, const vo
 
 fdas_status fdas_plan_destroy(fdas_plan_t pl) {
   if (!pl) return FDAS_OK;
+  if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) hipGraphDestroy(pl->graph);
   if (pl->h_desc_pinned || pl->h_lists_pinned) {
     hipSetDevice(pl->device);
     hipStreamSynchronize(pl->stream);

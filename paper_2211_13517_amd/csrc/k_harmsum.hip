@@ -67,6 +67,12 @@ struct HarmTile {
 template <int PDT>
 struct HarmCfg {
   static constexpr int JT = Store<PDT>::RBYTES == 2 ? 8 : 4;
+  // Tile order: groups of GROUP bands (about 48 trials) are swept over all
+  // column tiles, the bands of a group interleaved.  Bands that are close in
+  // z share the rows of the low harmonics, and a sweep's working set then
+  // stays in the L2/MALL (a cache model of this access pattern gives ~1.3
+  // plane reads from HBM, against ~4 when every column tile walks all bands).
+  static constexpr int GROUP = 48 / JT;
 };
 
 __device__ __forceinline__ int harm_row(int j0, int m, int k, int H) {
@@ -87,11 +93,12 @@ __global__ __launch_bounds__(kCells) void k_harmsum(HarmArgs a) {
 
   const SeriesDesc d = a.desc[blockIdx.z];
   const int nb = d.nbins;
-  // trial bands vary fastest across the grid, so the bands of one column tile
-  // (which share the rows of the low harmonics) run together and hit in L2
-  const int R0 = blockIdx.y * CW;
-  if (R0 >= nb - a.hmax) return;  // whole tile outside the searched band
-  const int jt0 = blockIdx.x * JT;
+  constexpr int G = HarmCfg<PDT>::GROUP;
+  const int nbx = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
+  const int grp = blockIdx.x / (nbx * G), inner = blockIdx.x % (nbx * G);
+  const int R0 = (inner / G) * CW;
+  const int jt0 = (grp * G + inner % G) * JT;
+  if (R0 >= nb - a.hmax || jt0 >= a.Z) return;  // whole tile outside the searched band
   const int jt1 = min(jt0 + JT, a.Z);
   const int tid = threadIdx.x;
   const RT* plane = reinterpret_cast<const RT*>(a.plane) + d.plane_off;
@@ -186,7 +193,11 @@ __global__ __launch_bounds__(256) void k_cand_sigma(fdas_candidate* __restrict__
 
 template <int PDT, int H>
 static void hs_launch(const HarmArgs& a, dim3 g, hipStream_t st) {
-  g.x = (a.Z + HarmCfg<PDT>::JT - 1) / HarmCfg<PDT>::JT;
+  constexpr int JT = HarmCfg<PDT>::JT, G = HarmCfg<PDT>::GROUP;
+  const int nby = (a.Z + JT - 1) / JT;
+  const int ngroups = (nby + G - 1) / G;
+  const int nbx = (a.max_bins + kCells - 1) / kCells;
+  g.x = (unsigned)((int64_t)ngroups * G * nbx);
   hipLaunchKernelGGL((k_harmsum<PDT, H>), g, dim3(kCells), 0, st, a);
 }
 
@@ -205,12 +216,14 @@ static hipError_t hs_h(const HarmArgs& a, dim3 g, hipStream_t st) {
 
 // The x-grid covers the longest series; blocks past a shorter series' end exit.
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st) {
-  const dim3 g(1, (max_bins + kCells - 1) / kCells, a.n_series);
+  HarmArgs b = a;
+  b.max_bins = max_bins;
+  const dim3 g(1, 1, a.n_series);
   hipError_t e;
   switch (pdt) {
-    case FDAS_F32: e = hs_h<FDAS_F32>(a, g, st); break;
-    case FDAS_BF16: e = hs_h<FDAS_BF16>(a, g, st); break;
-    case FDAS_F16: e = hs_h<FDAS_F16>(a, g, st); break;
+    case FDAS_F32: e = hs_h<FDAS_F32>(b, g, st); break;
+    case FDAS_BF16: e = hs_h<FDAS_BF16>(b, g, st); break;
+    case FDAS_F16: e = hs_h<FDAS_F16>(b, g, st); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || a.capacity == 0) return e;

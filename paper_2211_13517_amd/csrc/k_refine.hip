@@ -1,0 +1,287 @@
+// Row a12: Fourier-interpolated power P(r, z) at off-grid candidates, its
+// adjoint, and gradient-ascent refinement.
+//
+// y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),
+// w = m + ceil(|z|/2) (A_k = 0 outside the spectrum), P = |y|^2.
+// dy/dr = -sum A_k conj(d rho/dq), dy/dz = sum A_k conj(d rho/dz),
+// dP/dr = 2 Re(conj(y) dy/dr), dP/dz = 2 Re(conj(y) dy/dz), and the gradient
+// with respect to A_k (as d/dRe + i d/dIm) is 2 y rho(k - r, z).
+//
+// Derivatives of rho (phi(u) = -2 pi q u + pi z (u-1/2)^2):
+//  * |z| >= 0.05: integrating phi'(u) e^{i phi} by parts,
+//      I1 = int (u-1/2) e^{i phi} = (q rho + (e1 - e0)/(2 pi i)) / z,
+//      I2 = int (u-1/2)^2 e^{i phi} = (q I1 + ((e1 + e0)/2 - rho)/(2 pi i)) / z,
+//    e0 = e^{i phi(0)}, e1 = e^{i phi(1)}; d rho/dq = -2 pi i (I1 + rho/2), d rho/dz = i pi I2.
+//  * |z| < 0.05 (where those quotients cancel): expanding e^{i pi z v^2},
+//      rho = e^{-i pi q} sum_n c_n M_{2n},  c_n = (i pi z)^n / n!,
+//      d rho/dq = e^{-i pi q} sum_n c_n (-i pi M_{2n} - 2 pi i M_{2n+1}),
+//      d rho/dz = e^{-i pi q} i pi sum_n c_n M_{2n+2},
+//    with the moments M_k(q) = int_{-1/2}^{1/2} v^k e^{-2 pi i q v} dv from their
+//    Taylor series in 2 pi q (|2 pi q| < 10) or the upward recurrence of
+//    integration by parts.
+// All of this runs in FP64: on CDNA4 the FP64 vector rate equals the
+// unpacked FP32 rate, so FP64 costs no extra issue slots here.
+#include "fresnel.hpp"
+#include "launch.hpp"
+
+namespace fdas {
+
+constexpr double kZTaylor = 0.05;
+constexpr int kTaylorTerms = 9;           // n = 0..8
+constexpr int kMoments = 2 * kTaylorTerms + 2;
+
+__device__ inline void moments(double q, c64* M) {
+  const double c = 2.0 * kPi64 * q;
+  if (fabs(c) < 10.0) {
+    // M_k = sum_j (-i c)^j / j! mu_{k+j},  mu_n = 2^-n/(n+1) for even n, 0 for odd n
+    for (int k = 0; k < kMoments; ++k) {
+      c64 acc = {0.0, 0.0};
+      c64 t = {1.0, 0.0};  // (-i c)^j / j!
+      for (int j = 0; j < 60; ++j) {
+        const int n = k + j;
+        if ((n & 1) == 0) {
+          const double mu = ldexp(1.0, -n) / (n + 1);
+          acc = c64add(acc, c64scale(t, mu));
+        }
+        t = c64scale(c64mul(t, {0.0, -c}), 1.0 / (j + 1));
+        if (fabs(t.re) + fabs(t.im) < 1e-30) break;
+      }
+      M[k] = acc;
+    }
+  } else {
+    const c64 ep = cispi64(-q), em = cispi64(q);  // e^{-i c/2}, e^{+i c/2}
+    M[0] = {2.0 * sinpi(q) / c, 0.0};
+    const c64 inv_mic = {0.0, 1.0 / c};            // 1/(-i c) = i/c
+    double h = 1.0;
+    for (int k = 1; k < kMoments; ++k) {
+      h *= 0.5;
+      const double sg = (k & 1) ? -1.0 : 1.0;      // (-1/2)^k = sg * 2^-k
+      const c64 b = c64scale(c64sub(ep, c64scale(em, sg)), h);
+      // M_k = b/(-ic) + (k/(ic)) M_{k-1} = (b - k M_{k-1}) / (-ic)
+      M[k] = c64mul(c64sub(b, c64scale(M[k - 1], (double)k)), inv_mic);
+    }
+  }
+}
+
+struct RhoD {
+  c64 rho, dq, dz;
+};
+
+__device__ inline RhoD response_d64(double q, double z) {
+  RhoD o;
+  if (fabs(z) >= kZTaylor) {
+    o.rho = response64(q, z);
+    const c64 e0 = cispi64(0.25 * z);
+    const c64 e1 = cispi64(0.25 * z - 2.0 * q);
+    const c64 inv2pii = {0.0, -1.0 / (2.0 * kPi64)};  // 1/(2 pi i)
+    const c64 i1 = c64scale(c64add(c64scale(o.rho, q), c64mul(c64sub(e1, e0), inv2pii)), 1.0 / z);
+    const c64 mid = c64sub(c64scale(c64add(e1, e0), 0.5), o.rho);
+    const c64 i2 = c64scale(c64add(c64scale(i1, q), c64mul(mid, inv2pii)), 1.0 / z);
+    const c64 s = c64add(i1, c64scale(o.rho, 0.5));
+    o.dq = c64mul({0.0, -2.0 * kPi64}, s);
+    o.dz = c64mul({0.0, kPi64}, i2);
+    return o;
+  }
+  c64 M[kMoments];
+  moments(q, M);
+  c64 r = {0.0, 0.0}, dq1 = {0.0, 0.0}, dz1 = {0.0, 0.0};
+  c64 cn = {1.0, 0.0};
+  for (int n = 0; n < kTaylorTerms; ++n) {
+    r = c64add(r, c64mul(cn, M[2 * n]));
+    dq1 = c64add(dq1, c64mul(cn, M[2 * n + 1]));
+    dz1 = c64add(dz1, c64mul(cn, M[2 * n + 2]));
+    cn = c64scale(c64mul(cn, {0.0, kPi64 * z}), 1.0 / (n + 1));
+  }
+  const c64 ph = cispi64(-q);
+  o.rho = c64mul(ph, r);
+  o.dq = c64mul(ph, c64add(c64mul({0.0, -kPi64}, r), c64mul({0.0, -2.0 * kPi64}, dq1)));
+  o.dz = c64mul(ph, c64mul({0.0, kPi64}, dz1));
+  return o;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int SDT>
+__device__ inline c64 spec_at(const void* spec, int64_t nb, int64_t k) {
+  using SS = Store<SDT>;
+  if (k < 0 || k >= nb) return {0.0, 0.0};
+  const c32 v = SS::unpack(reinterpret_cast<const typename SS::cplx_t*>(spec)[k]);
+  return {(double)v.re, (double)v.im};
+}
+
+struct RzEval {
+  c64 y, dydr, dydz;
+};
+
+// One wavefront evaluates y (and optionally its r, z derivatives) at (r, z).
+template <int SDT, bool GRAD>
+__device__ inline RzEval rz_eval(const void* spec, int64_t nb, double r, double z, int margin) {
+  const int64_t k0 = (int64_t)floor(r);
+  const int w = margin + (int)ceil(fabs(z) * 0.5);
+  const int lane = threadIdx.x & 63;
+  c64 y = {0, 0}, dr = {0, 0}, dz = {0, 0};
+  for (int t = lane; t < 2 * w; t += 64) {
+    const int64_t k = k0 - w + 1 + t;
+    const c64 a = spec_at<SDT>(spec, nb, k);
+    if (a.re == 0.0 && a.im == 0.0) continue;
+    if (GRAD) {
+      const RhoD d = response_d64((double)k - r, z);
+      y = c64add(y, c64mul(a, c64conj(d.rho)));
+      dr = c64sub(dr, c64mul(a, c64conj(d.dq)));
+      dz = c64add(dz, c64mul(a, c64conj(d.dz)));
+    } else {
+      y = c64add(y, c64mul(a, c64conj(response64((double)k - r, z))));
+    }
+  }
+  RzEval e;
+  e.y = {wave_sum(y.re), wave_sum(y.im)};
+  if (GRAD) {
+    e.dydr = {wave_sum(dr.re), wave_sum(dr.im)};
+    e.dydz = {wave_sum(dz.re), wave_sum(dz.im)};
+  }
+  return e;
+}
+
+template <int SDT>
+__global__ __launch_bounds__(256) void k_rz_power(const void* spec, int64_t nb, const float* r, const float* z, int64_t n,
+                                                  int margin, float* p, c64* y_out) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const RzEval e = rz_eval<SDT, false>(spec, nb, (double)r[c], (double)z[c], margin);
+  if ((threadIdx.x & 63) == 0) {
+    p[c] = (float)(e.y.re * e.y.re + e.y.im * e.y.im);
+    if (y_out) y_out[c] = e.y;
+  }
+}
+
+constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point unit of the spectrum-gradient accumulator
+
+template <int SDT>
+__global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, const float* r, const float* z,
+                                                 const c64* y_in, const float* gp, int64_t n, int margin,
+                                                 float* gr, float* gz, unsigned long long* acc) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const double rr = (double)r[c], zz = (double)z[c];
+  const RzEval e = rz_eval<SDT, true>(spec, nb, rr, zz, margin);
+  const c64 y = y_in ? y_in[c] : e.y;
+  const double g = (double)gp[c];
+  if ((threadIdx.x & 63) == 0) {
+    gr[c] = (float)(g * 2.0 * (y.re * e.dydr.re + y.im * e.dydr.im));
+    gz[c] = (float)(g * 2.0 * (y.re * e.dydz.re + y.im * e.dydz.im));
+  }
+  if (!acc) return;
+  // dP/dA_k = 2 y rho(k - r, z), accumulated in 2^-40 fixed point: integer
+  // addition is associative, so the sum does not depend on arrival order.
+  const int64_t k0 = (int64_t)floor(rr);
+  const int w = margin + (int)ceil(fabs(zz) * 0.5);
+  for (int t = threadIdx.x & 63; t < 2 * w; t += 64) {
+    const int64_t k = k0 - w + 1 + t;
+    if (k < 0 || k >= nb) continue;
+    const c64 v = c64scale(c64mul(y, response64((double)k - rr, zz)), 2.0 * g);
+    atomicAdd(acc + 2 * k, (unsigned long long)(long long)llrint(v.re * kFixScale));
+    atomicAdd(acc + 2 * k + 1, (unsigned long long)(long long)llrint(v.im * kFixScale));
+  }
+}
+
+__global__ void k_fix_clear(unsigned long long* acc, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc[i] = 0ull;
+}
+
+__global__ void k_fix_to_float(const unsigned long long* acc, float* out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)((double)(long long)acc[i] / kFixScale);
+}
+
+// Preconditioned gradient ascent: near a peak P ~ P0 (1 - a dr^2 - b dz^2)
+// with a = pi^2/3 (sinc main lobe) and b = pi^2/180 (quadratic-phase
+// mismatch), so the step (g_r / (2 a P), g_z / (2 b P)) is Newton's step for
+// that model; it is clamped and halved until P increases.
+template <int SDT>
+__global__ __launch_bounds__(256) void k_refine(const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters,
+                                                int margin, double* p_final) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  constexpr double A = kPi64 * kPi64 / 3.0, B = kPi64 * kPi64 / 180.0;
+  double rr = (double)r[c], zz = (double)z[c];
+  RzEval e = rz_eval<SDT, true>(spec, nb, rr, zz, margin);
+  double P = e.y.re * e.y.re + e.y.im * e.y.im;
+  for (int it = 0; it < iters && P > 0.0; ++it) {
+    const double gr = 2.0 * (e.y.re * e.dydr.re + e.y.im * e.dydr.im);
+    const double gz = 2.0 * (e.y.re * e.dydz.re + e.y.im * e.dydz.im);
+    double sr = fmin(fmax(gr / (2.0 * A * P), -0.25), 0.25);
+    double sz = fmin(fmax(gz / (2.0 * B * P), -2.0), 2.0);
+    bool moved = false;
+    for (int ls = 0; ls < 8; ++ls) {
+      const RzEval t = rz_eval<SDT, true>(spec, nb, rr + sr, zz + sz, margin);
+      const double Pt = t.y.re * t.y.re + t.y.im * t.y.im;
+      if (Pt > P) {
+        rr += sr;
+        zz += sz;
+        P = Pt;
+        e = t;
+        moved = true;
+        break;
+      }
+      sr *= 0.5;
+      sz *= 0.5;
+    }
+    if (!moved || (fabs(sr) < 1e-7 && fabs(sz) < 1e-6)) break;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    r[c] = (float)rr;
+    z[c] = (float)zz;
+  }
+  // final FP64 evaluation at the stored (float) position
+  const RzEval f = rz_eval<SDT, false>(spec, nb, (double)(float)rr, (double)(float)zz, margin);
+  if ((threadIdx.x & 63) == 0) p_final[c] = f.y.re * f.y.re + f.y.im * f.y.im;
+}
+
+hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const float* r, const float* z, int64_t n, int margin,
+                           float* p, c64* y, hipStream_t st) {
+  const dim3 g((unsigned)((n + 3) / 4));
+  switch (sdt) {
+    case FDAS_F32: hipLaunchKernelGGL((k_rz_power<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, n, margin, p, y); break;
+    case FDAS_BF16: hipLaunchKernelGGL((k_rz_power<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, n, margin, p, y); break;
+    case FDAS_F16: hipLaunchKernelGGL((k_rz_power<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, n, margin, p, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const float* r, const float* z, const c64* y,
+                          const float* gp, int64_t n, int margin, float* gr, float* gz, float* gspec,
+                          unsigned long long* acc, hipStream_t st) {
+  const dim3 g((unsigned)((n + 3) / 4));
+  if (gspec) {
+    hipLaunchKernelGGL(k_fix_clear, dim3(1024), dim3(256), 0, st, acc, 2 * nb);
+  }
+  unsigned long long* a = gspec ? acc : nullptr;
+  switch (sdt) {
+    case FDAS_F32: hipLaunchKernelGGL((k_rz_grad<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
+    case FDAS_BF16: hipLaunchKernelGGL((k_rz_grad<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
+    case FDAS_F16: hipLaunchKernelGGL((k_rz_grad<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (gspec) hipLaunchKernelGGL(k_fix_to_float, dim3(1024), dim3(256), 0, st, acc, gspec, 2 * nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(int sdt, const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters, int margin,
+                         double* p_final, hipStream_t st) {
+  const dim3 g((unsigned)((n + 3) / 4));
+  switch (sdt) {
+    case FDAS_F32: hipLaunchKernelGGL((k_refine<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, n, iters, margin, p_final); break;
+    case FDAS_BF16: hipLaunchKernelGGL((k_refine<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, n, iters, margin, p_final); break;
+    case FDAS_F16: hipLaunchKernelGGL((k_refine<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, n, iters, margin, p_final); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fdas

@@ -80,8 +80,22 @@ struct HarmArgs {
   float tau[5];
   double z_min, z_step;
   int32_t n_series, Z, j0, n_harm, r_lo, hmax;
+  int32_t max_bins;  // longest series in the batch (sets the tile grid)
 };
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
+
+// a12
+hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const float* r, const float* z, int64_t n, int margin,
+                           float* p, c64* y, hipStream_t st);
+hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const float* r, const float* z, const c64* y,
+                          const float* gp, int64_t n, int margin, float* gr, float* gz, float* gspec,
+                          unsigned long long* acc, hipStream_t st);
+hipError_t launch_refine(int sdt, const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters, int margin,
+                         double* p_final, hipStream_t st);
+
+// small helpers (fill kernels are graph-capture safe, unlike memset nodes)
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t value, hipStream_t st);
+hipError_t launch_fill_noise(void* spec, int sdt, int64_t nbins, uint64_t seed, hipStream_t st);
 
 // self-test hook: batched complex FFT of size L
 hipError_t launch_test_fft(int L, int dir, const c32* in, c32* out, int64_t batch, const c32* tw, hipStream_t st);

@@ -59,6 +59,27 @@ def make_series(n: int, injections: Sequence[Injection], cfg_seed: int, series_i
     return x.astype(np.float32)
 
 
+def make_series_device(n: int, injections: Sequence[Injection], cfg_seed: int, series_index: int,
+                       noise_sd: float = 1.0, device: str = "cuda", chunk: int = 64):
+    """Same recipe as make_series (same noise bits, FP64 sum, one cast), with
+    the injections evaluated on a torch device; returns a float32 tensor there.
+    For series carrying thousands of injections."""
+    import torch
+    x = torch.zeros(n, dtype=torch.float64, device=device)
+    if noise_sd > 0:
+        x += torch.from_numpy(noise_sd * rng_for(cfg_seed, series_index).standard_normal(n)).to(device)
+    u = torch.arange(n, dtype=torch.float64, device=device) / n
+    for i in range(0, len(injections), chunk):
+        part = injections[i:i + chunk]
+        a = torch.tensor([j.amp for j in part], dtype=torch.float64, device=device)
+        r0 = torch.tensor([j.r0 for j in part], dtype=torch.float64, device=device)
+        z = torch.tensor([j.z for j in part], dtype=torch.float64, device=device)
+        ph = torch.tensor([j.phase for j in part], dtype=torch.float64, device=device)
+        for k in range(len(part)):
+            x += a[k] * torch.cos(2.0 * np.pi * (r0[k] * u + 0.5 * z[k] * u * u) + ph[k])
+    return x.to(torch.float32)
+
+
 # ---------------------------------------------------------------- configurations
 
 def small_case(seed: int = 1, noise: bool = True):
@@ -134,6 +155,39 @@ def batch_series(lengths: Sequence[int], seed: int, inj_per_series=(0, 2),
         xs.append(make_series(n, inj, seed, i))
         truths.append(inj)
     return xs, truths
+
+
+def batch_injections(lengths: Sequence[int], seed: int, inj_per_series=(0, 2), amp=(0.01, 0.05), z_abs=90.0,
+                     scale_decimated=True) -> List[List[Injection]]:
+    """The injections batch_series would draw, without generating the noise."""
+    nmax = max(lengths)
+    truths = []
+    for i, n in enumerate(lengths):
+        rng = rng_for(seed, 30_000 + i)
+        k = int(rng.integers(inj_per_series[0], inj_per_series[1] + 1))
+        inj = draw_injections(rng, k, n, amp=amp, z_abs=z_abs) if k else []
+        if scale_decimated:
+            d = nmax // n
+            for j in inj:
+                j.amp *= math.sqrt(d)
+        truths.append(inj)
+    return truths
+
+
+def fill_series_device(out, injections: Sequence[Injection], cfg_seed: int, series_index: int):
+    """Large-batch variant of make_series for benchmarks: the N(0,1) noise comes
+    from torch's device generator seeded with (cfg_seed, series_index) instead
+    of numpy's, the injections are added in float64, and the sum is cast into
+    the float32 device tensor ``out``."""
+    import torch
+    n = out.numel()
+    g = torch.Generator(device=out.device)
+    g.manual_seed(int(np.random.SeedSequence([cfg_seed, series_index]).generate_state(1, np.uint64)[0]) & ((1 << 63) - 1))
+    x = torch.randn(n, dtype=torch.float64, device=out.device, generator=g)
+    u = torch.arange(n, dtype=torch.float64, device=out.device) / n
+    for j in injections:
+        x += j.amp * torch.cos(2.0 * np.pi * (j.r0 * u + 0.5 * j.z * u * u) + j.phase)
+    out.copy_(x.to(torch.float32))
 
 
 def concat(xs: Sequence[np.ndarray]):

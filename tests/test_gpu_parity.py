@@ -279,3 +279,58 @@ def test_nonfinite_input_is_reported(lib):
     with pytest.raises(lib.FdasError, match="NaN"):
         pl.check()
     pl.check()  # the latch clears
+
+
+# ---------------------------------------------------------------- a11: batch, graph, autotune
+
+def test_search_graph_replays_match_eager(lib):
+    """fdas_search captured into a HIP graph: every replay (with eager work and
+    synchronisations in between) reproduces the eager result bit for bit."""
+    import torch
+    n = 1 << 18
+    lens = [n, n // 2, n // 4, n]
+    xs, truths = synth.batch_series(lens, seed=51, amp=(0.05, 0.08))
+    flat, offs, lens_a = synth.concat(xs)
+    say("fdas_search graph", lens)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pl = lib.Plan(n_samples=n, max_batch_samples=int(lens_a.sum()), z_min=-32.0, z_max=32.0, z_step=2.0,
+                      n_harmonics=8, segment_len=1024, store="bf16", plane="bf16", stream=stream)
+        xt = torch.from_numpy(flat).to("cuda")
+        tot = int(lens_a.sum()) // 2
+        P0, P1 = pl.new_plane(tot), pl.new_plane(tot)
+        c0 = torch.zeros((1 << 15, 8), dtype=torch.int32, device="cuda")
+        c1 = torch.zeros_like(c0)
+        k0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k1 = torch.zeros_like(k0)
+        pl.search(xt, offs, lens_a, P0, c0, k0, use_graph=False)
+        pl.check(k0, c0.shape[0])
+        want = sorted(map(tuple, lib.candidates_to_numpy(c0, int(k0.item())).tolist()))
+        for rep in range(3):
+            P1.fill_(0)
+            k1.fill_(7)
+            pl.search(xt, offs, lens_a, P1, c1, k1, use_graph=True)
+            pl.check(k1, c1.shape[0])
+            assert torch.equal(P0, P1), rep
+            got = sorted(map(tuple, lib.candidates_to_numpy(c1, int(k1.item())).tolist()))
+            assert got == want, rep
+            torch.cuda.synchronize()
+            _ = (P0.float().sum() + 1).item()   # eager work between replays
+        assert len(want) > 0
+
+
+def test_autotune_picks_a_valid_configuration(lib):
+    import torch
+    n = 1 << 18
+    say("fdas_autotune", n)
+    best = lib.autotune(cache="/tmp/fdas_tune_test.json", n_samples=n, z_min=-32.0, z_max=32.0, z_step=1.0,
+                        store="bf16", plane="bf16")
+    assert best.segment_len in (1024, 2048, 4096, 8192)
+    x = synth.make_series(n, [synth.Injection(0.05, 7000.0, 21.0, 0.3)], 52, 0)
+    pl = lib.Plan(params=best, n_samples=n)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
+    zs = o.z_grid(-32, 32, 1)
+    ref = o.power_plane(o.normalise(o.spectrum(x), "median"), zs, rows=[0, 25, 32, 53, 64])
+    got = P.view(pl.Z, n // 2).float().cpu().numpy()[[0, 25, 32, 53, 64]]
+    e = o.power_errors(got, ref, tau1=o.threshold(1))
+    assert e["max_rel_det"] < 3e-2
