@@ -168,12 +168,13 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
  * candidates (section 2.1's matched filter evaluated between grid points):
  *   y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),
  *   w = kernel_margin + ceil(|z|/2) (32 bins at z = 0), A_k = 0 outside [0, n_bins),
- *   P = |y|^2, evaluated in FP64 and returned as float p[i].
+ *   P = |y|^2, evaluated in FP64.
  * spectrum: store_dtype complex [n_bins] (one series, e.g. from fdas_spectrum);
- * r, z, p: float [n] device arrays; y_out (optional, complex128 [n]) keeps y for
- * the adjoint.  n_bins <= max_batch_samples / 2. */
-fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const float *r, const float *z,
-                          int64_t n, float *p, void *y_out);
+ * r, z, p: double [n] device arrays (positions need FP64: bins reach 2^22);
+ * y_out (optional, complex128 [n]) keeps y for the adjoint.
+ * n_bins <= max_batch_samples / 2. */
+fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r, const double *z,
+                          int64_t n, double *p, void *y_out);
 
 /* Row a12, adjoint: given the upstream gradient grad_p[i] of a real loss with
  * respect to p[i], writes grad_r[i] = grad_p 2 Re(conj(y) dy/dr),
@@ -183,16 +184,16 @@ fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins
  * the gradient with respect to A_k as d/dRe + i d/dIm.  That sum is formed in
  * 2^-40 fixed point with integer atomics, so it is bitwise deterministic.
  * y: the forward's y_out, or NULL to recompute it.  Uses the workspace. */
-fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const float *r,
-                               const float *z, const void *y, const float *grad_p, int64_t n, float *grad_r,
-                               float *grad_z, void *grad_spectrum);
+fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r,
+                               const double *z, const void *y, const double *grad_p, int64_t n, double *grad_r,
+                               double *grad_z, void *grad_spectrum);
 
 /* Row a12, refinement: n_iter steps of preconditioned gradient ascent of
  * P(r, z) per candidate (step (dP/dr / (2 a P), dP/dz / (2 b P)) with
  * a = pi^2/3, b = pi^2/180, clamped to 0.25 bin and 2 z, halved until P
- * grows), r and z updated in place (float [n]), and the final power evaluated
+ * grows), r and z updated in place (double [n]), and the final power evaluated
  * in FP64 at the returned position into p_final (double [n]). */
-fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, float *r, float *z, int64_t n,
+fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, double *r, double *z, int64_t n,
                         int32_t n_iter, double *p_final);
 
 /* Rows a1-a10 for one batch in one call: resets *d_count (with a kernel),

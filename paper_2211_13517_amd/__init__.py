@@ -256,12 +256,12 @@ class Plan:
 
     # ------------------------------------------------------------ refinement
     def rz_power(self, spectrum, r, z, keep_y: bool = True):
-        """P(r, z) (float32 [n]) and y (complex128 [n]) at off-grid candidates."""
+        """P(r, z) (float64 [n]) and y (complex128 [n]) at off-grid candidates."""
         import torch
-        r = r.contiguous().float()
-        z = z.contiguous().float()
+        r = r.contiguous().double()
+        z = z.contiguous().double()
         n = r.numel()
-        p = torch.empty(n, dtype=torch.float32, device=self.device)
+        p = torch.empty(n, dtype=torch.float64, device=self.device)
         y = torch.empty(n, dtype=torch.complex128, device=self.device) if keep_y else None
         nb = spectrum.shape[0]
         self._check(self.lib.fdas_rz_power(self.handle, c_void_p(spectrum.data_ptr()), nb, c_void_p(r.data_ptr()),
@@ -272,12 +272,12 @@ class Plan:
     def rz_power_grad(self, spectrum, r, z, grad_p, y=None, want_spectrum: bool = True):
         """(grad_r, grad_z, grad_spectrum complex64 [n_bins] or None) for upstream grad_p."""
         import torch
-        r = r.contiguous().float()
-        z = z.contiguous().float()
-        gp = grad_p.contiguous().float()
+        r = r.contiguous().double()
+        z = z.contiguous().double()
+        gp = grad_p.contiguous().double()
         n = r.numel()
-        gr = torch.empty(n, dtype=torch.float32, device=self.device)
-        gz = torch.empty(n, dtype=torch.float32, device=self.device)
+        gr = torch.empty(n, dtype=torch.float64, device=self.device)
+        gz = torch.empty(n, dtype=torch.float64, device=self.device)
         nb = spectrum.shape[0]
         gs = torch.empty(nb, dtype=torch.complex64, device=self.device) if want_spectrum else None
         self._check(self.lib.fdas_rz_power_grad(
@@ -289,8 +289,8 @@ class Plan:
     def refine(self, spectrum, r, z, n_iter: int = 30):
         """Gradient-ascent refinement: returns (r, z, p_final float64)."""
         import torch
-        r = r.clone().contiguous().float()
-        z = z.clone().contiguous().float()
+        r = r.clone().contiguous().double()
+        z = z.clone().contiguous().double()
         n = r.numel()
         pf = torch.empty(n, dtype=torch.float64, device=self.device)
         self._check(self.lib.fdas_refine(self.handle, c_void_p(spectrum.data_ptr()), spectrum.shape[0],

@@ -312,10 +312,21 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
   if (pl->p.templates_per_tile > 0) {
     G = (pl->Z + pl->p.templates_per_tile - 1) / pl->p.templates_per_tile;
   } else {
-    // concurrently resident tile owners (wavefronts or blocks) on the device
+    // W tile owners take tiles round-robin, so with T = nseg * G tiles the
+    // launch lasts ceil(T/W) rounds of one tile (Z/G inverse FFTs plus the
+    // segment's forward FFT): choose the G that minimises that product.
     const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
-    const int64_t units = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
-    G = (int)std::min<int64_t>(pl->Z, std::max<int64_t>(1, (8 * units + nseg_total - 1) / nseg_total));
+    const int64_t W = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
+    double best = 1e300;
+    G = 1;
+    for (int g = 1; g <= pl->Z; ++g) {
+      const double rounds = std::ceil((double)nseg_total * g / (double)W);
+      const double t = rounds * ((double)pl->Z / g + 1.0);
+      if (t < best - 1e-9) {
+        best = t;
+        G = g;
+      }
+    }
   }
   pl->G = G;
   pl->desc.resize(n);
@@ -720,8 +731,8 @@ static fdas_status rz_check(fdas_plan_t pl, const void* spec, int64_t nb, int64_
   return FDAS_OK;
 }
 
-fdas_status fdas_rz_power(fdas_plan_t pl, const void* spec, int64_t nb, const float* r, const float* z, int64_t n,
-                          float* p, void* y_out) {
+fdas_status fdas_rz_power(fdas_plan_t pl, const void* spec, int64_t nb, const double* r, const double* z, int64_t n,
+                          double* p, void* y_out) {
   if (!pl) return FDAS_ERR_ARG;
   fdas_status s = rz_check(pl, spec, nb, n);
   if (s != FDAS_OK) return s;
@@ -732,8 +743,8 @@ fdas_status fdas_rz_power(fdas_plan_t pl, const void* spec, int64_t nb, const fl
   return FDAS_OK;
 }
 
-fdas_status fdas_rz_power_grad(fdas_plan_t pl, const void* spec, int64_t nb, const float* r, const float* z,
-                               const void* y, const float* grad_p, int64_t n, float* grad_r, float* grad_z,
+fdas_status fdas_rz_power_grad(fdas_plan_t pl, const void* spec, int64_t nb, const double* r, const double* z,
+                               const void* y, const double* grad_p, int64_t n, double* grad_r, double* grad_z,
                                void* grad_spectrum) {
   if (!pl) return FDAS_ERR_ARG;
   fdas_status s = rz_check(pl, spec, nb, n);
@@ -747,7 +758,7 @@ fdas_status fdas_rz_power_grad(fdas_plan_t pl, const void* spec, int64_t nb, con
   return FDAS_OK;
 }
 
-fdas_status fdas_refine(fdas_plan_t pl, const void* spec, int64_t nb, float* r, float* z, int64_t n, int32_t n_iter,
+fdas_status fdas_refine(fdas_plan_t pl, const void* spec, int64_t nb, double* r, double* z, int64_t n, int32_t n_iter,
                         double* p_final) {
   if (!pl) return FDAS_ERR_ARG;
   fdas_status s = rz_check(pl, spec, nb, n);

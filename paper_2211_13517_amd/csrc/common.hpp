@@ -93,6 +93,17 @@ __device__ __forceinline__ void wave_lds_fence() {
   asm volatile("" ::: "memory");
 }
 
+// Direct global-to-LDS load of 16 bytes per lane (gfx950): lane i's bytes go
+// to lds_wave_base + 16 i, lds_wave_base being wave-uniform; inactive lanes
+// write nothing.  The data is visible to the block after a barrier (the
+// compiler waits for the loads there).  The builtin exists only in the
+// device pass, so the host pass sees an empty body.
+__device__ __forceinline__ void load_lds16(const void* src, void* lds_wave_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+#endif
+}
+
 // Loads and stores at a uniform base plus a 32-bit byte offset, so that the
 // compiler can address with one offset register and immediates.
 template <typename T>

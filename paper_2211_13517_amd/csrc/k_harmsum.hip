@@ -45,124 +45,241 @@ __device__ inline double sigma_from_log_tail(double lq) {
   return x;
 }
 
-// Tiling: a block owns CW consecutive cells R in [R0, R0 + CW) (R0 a multiple
-// of CW) for JT consecutive acceleration trials.  For R0 + i, harmonic k reads
-// bin r_k = k R0 / H + floor((2 k i + H) / (2 H)), so the tile needs, for each
-// k, the strip of bins [k R0 / H, k R0 / H + CW k / H] of the rows j_k(j) of
-// its trials, which form a contiguous range of at most floor(k (JT-1)/H) + 2
-// rows (j_k is monotone in j).  The block copies every such strip into LDS in
-// one burst of aligned 16-byte loads (raw storage type), synchronises once and
-// evaluates its CW x JT cells from LDS.
-constexpr int kCells = 256;
+// Tiling.  A block owns CW consecutive cells R in [R0, R0 + CW) (R0 a
+// multiple of CW) for the 16 trials of one band m in [16u, 16u + 16), bands
+// aligned to z = 0.  Because m_k(m + H) = m_k(m) + k for m >= 0 (and the
+// mirror image below zero), the harmonic-k row used by trial t of band u is
+//   base_k + rel_k(t),  base_k = j0 + 16 k u / H,
+// with rel_k(t) = floor((2kt + H)/(2H)) for u >= 0 and ceil((2kt - H)/(2H))
+// for u < 0: a compile-time pattern.  Likewise harmonic k of cell R0 + i
+// reads bin k R0 / H + floor((2ki + H)/(2H)).  The block copies, for every
+// k, the rows base_k .. base_k + rows(k) - 1 of the bin strip it needs into
+// LDS with aligned 16-byte loads, synchronises once, and then evaluates its
+// CW x 16 cells with LDS reads whose offsets are all immediates.
+constexpr int kBand = 16;
 
-template <int H, int CW, int JT, int CH>
+template <int H, int CW, int CH>
 struct HarmTile {
-  static constexpr int rows(int k) { return (k * (JT - 1)) / H + 2; }             // max distinct rows of harmonic k
-  static constexpr int chunks(int k) { return (CW * k / H + 1 + 2 * CH - 2) / CH; } // 16-byte chunks per strip row
-  static constexpr int pitch(int k) { return chunks(k) * CH; }                      // elements per strip row
+  static constexpr int rows(int k) { return (2 * k * (kBand - 1) + H) / (2 * H) + 1; }
+  static constexpr int chunks(int k) { return (CW * k / H + 1 + CH - 1) / CH; }  // 16-byte chunks per strip row
+  static constexpr int pitch(int k) { return chunks(k) * CH; }                     // elements per strip row
   static constexpr int off(int k) { return k <= 1 ? 0 : off(k - 1) + rows(k - 1) * pitch(k - 1); }
-  static constexpr int SIZE = off(H + 1);                                            // elements of LDS
+  static constexpr int SIZE = off(H + 1);                                           // elements of LDS
+  // strip row of harmonic k for trial t of a band below (neg) or above z = 0
+  static constexpr int rel(int k, int t, bool neg) {
+    return neg ? (2 * k * t - H <= 0 ? 0 : (2 * k * t - H + 2 * H - 1) / (2 * H)) : (2 * k * t + H) / (2 * H);
+  }
 };
 
 template <int PDT>
 struct HarmCfg {
-  static constexpr int JT = Store<PDT>::RBYTES == 2 ? 8 : 4;
-  // Tile order: groups of GROUP bands (about 48 trials) are swept over all
-  // column tiles, the bands of a group interleaved.  Bands that are close in
-  // z share the rows of the low harmonics, and a sweep's working set then
+  static constexpr int CW = Store<PDT>::RBYTES == 2 ? 256 : 128;  // cells per tile = threads per block
+  // Tile order: groups of GROUP bands (48 trials) are swept over all column
+  // tiles, the bands of a group interleaved.  Bands that are close in z
+  // share the rows of the low harmonics, and a sweep's working set then
   // stays in the L2/MALL (a cache model of this access pattern gives ~1.3
   // plane reads from HBM, against ~4 when every column tile walks all bands).
-  static constexpr int GROUP = 48 / JT;
+  static constexpr int GROUP = 3;
 };
 
-__device__ __forceinline__ int harm_row(int j0, int m, int k, int H) {
-  const int am = m < 0 ? -m : m;
-  const int mk = (2 * k * am + H) / (2 * H);
-  return j0 + (m < 0 ? -mk : mk);
+__device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0 ? a : a - b + 1) / b; }
+
+// Nested stage sums: stage 0 is harmonic H alone; stage st adds the odd
+// multiples of H / 2^st, so the sum handed to sink(st, S) covers
+// k = H/2^st, 2 H/2^st, ..., H.
+// The harmonic values are read from LDS at byte offsets boff[k-1] + OFF(k).
+//  * FP32 planes: plain FP32 additions in that order.
+//  * 16-bit planes: the values are read in pairs into one register (stage 1
+//    pairs H with H/2; later stages pair consecutive odd multiples) and each
+//    pair is added to the running sum by one FP32-accumulating two-term dot
+//    product with (1, 1), the products being exact.
+template <int PDT>
+__device__ __forceinline__ uint32_t lds_u16(const char* lds, int boff) {
+  return *reinterpret_cast<const uint16_t*>(lds + boff);
+}
+
+template <int PDT, int H, typename OFF, typename SINK>
+__device__ __forceinline__ void stage_sums(const char* lds, const int* boff, OFF off, SINK sink) {
+  using PS = Store<PDT>;
+  using RT = typename PS::real_t;
+  constexpr int NST = ilog2(H) + 1;
+  auto at = [&](auto kc) -> const char* { return lds + boff[decltype(kc)::value - 1] + off(kc); };
+  if constexpr (PS::RBYTES == 4) {
+    float s = *reinterpret_cast<const float*>(at(std::integral_constant<int, H>{}));
+    sink(0, s);
+    static_for<1, NST>([&](auto sc) {
+      constexpr int st = decltype(sc)::value;
+      constexpr int step = H >> st;
+      static_for<0, (1 << st) / 2>([&](auto ic) {
+        constexpr int k = step * (2 * decltype(ic)::value + 1);
+        s += *reinterpret_cast<const float*>(at(std::integral_constant<int, k>{}));
+      });
+      sink(st, s);
+    });
+  } else {
+    typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+    auto pair = [&](auto ka, auto kb) {
+      us2 v;
+      v.x = *reinterpret_cast<const uint16_t*>(at(ka));
+      v.y = *reinterpret_cast<const uint16_t*>(at(kb));
+      return __builtin_bit_cast(uint32_t, v);
+    };
+    auto dot = [](uint32_t w, float acc) {
+      if constexpr (PDT == FDAS_BF16) {
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf2, w), __builtin_bit_cast(bf2, 0x3f803f80u), acc,
+                                               false);
+      } else {
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, w), __builtin_bit_cast(h2, 0x3c003c00u), acc, false);
+      }
+    };
+    if constexpr (H == 1) {
+      sink(0, PS::unpack_real((RT)lds_u16<PDT>(lds, boff[0] + off(std::integral_constant<int, 1>{}))));
+    } else {
+      const uint32_t w1 = pair(std::integral_constant<int, H / 2>{}, std::integral_constant<int, H>{});
+      sink(0, PS::unpack_real((RT)(w1 >> 16)));
+      float s = dot(w1, 0.f);
+      sink(1, s);
+      static_for<2, NST>([&](auto sc) {
+        constexpr int st = decltype(sc)::value;
+        constexpr int step = H >> st;
+        static_for<0, (1 << st) / 4>([&](auto ic) {
+          constexpr int ka = step * (4 * decltype(ic)::value + 1), kb = ka + 2 * step;
+          s = dot(pair(std::integral_constant<int, ka>{}, std::integral_constant<int, kb>{}), s);
+        });
+        sink(st, s);
+      });
+    }
+  }
 }
 
 template <int PDT, int H>
-__global__ __launch_bounds__(kCells) void k_harmsum(HarmArgs a) {
+__global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   using PS = Store<PDT>;
   using RT = typename PS::real_t;
   constexpr int NST = ilog2(H) + 1;
   constexpr int CH = 16 / (int)sizeof(RT);
-  constexpr int CW = kCells, JT = HarmCfg<PDT>::JT;
-  using HT = HarmTile<H, CW, JT, CH>;
+  constexpr int CW = HarmCfg<PDT>::CW, G = HarmCfg<PDT>::GROUP;
+  using HT = HarmTile<H, CW, CH>;
   __shared__ __align__(16) RT strip[HT::SIZE];
 
   const SeriesDesc d = a.desc[blockIdx.z];
   const int nb = d.nbins;
-  constexpr int G = HarmCfg<PDT>::GROUP;
-  const int nbx = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
-  const int grp = blockIdx.x / (nbx * G), inner = blockIdx.x % (nbx * G);
+  const int ncol = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
+  const int grp = blockIdx.x / (ncol * G), inner = blockIdx.x % (ncol * G);
   const int R0 = (inner / G) * CW;
-  const int jt0 = (grp * G + inner % G) * JT;
-  if (R0 >= nb - a.hmax || jt0 >= a.Z) return;  // whole tile outside the searched band
-  const int jt1 = min(jt0 + JT, a.Z);
+  const int u = floordiv(-a.j0, kBand) + grp * G + inner % G;
+  const int jt0 = a.j0 + kBand * u;  // trial of t = 0
+  if (R0 >= nb - a.hmax || jt0 >= a.Z) return;  // whole tile outside the searched region
+  const int t_lo = max(0, -jt0), t_hi = min(kBand, a.Z - jt0);
   const int tid = threadIdx.x;
   const RT* plane = reinterpret_cast<const RT*>(a.plane) + d.plane_off;
 
-  // copy the strips
+  // Copy the strips with direct global-to-LDS 16-byte loads: item f of
+  // harmonic k (row f / NCH, chunk f % NCH) lands at byte off(k) * sizeof(RT)
+  // + 16 f, so a wave's 64 items are contiguous in LDS from a wave-uniform
+  // base, and every load of the block is in flight before the one wait at
+  // the barrier.  Rows outside the plane are never read by a valid trial.
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
   static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
-    const int rlo = harm_row(a.j0, jt0 - a.j0, k, H);
-    const int rhi = harm_row(a.j0, jt1 - 1 - a.j0, k, H);
-    const int nitems = (rhi - rlo + 1) * NCH;
-    const int cs = (k * (R0 / H)) & ~(CH - 1);
+    const int base = a.j0 + (kBand / H) * k * u;
+    const int cs = k * (R0 / H);
 #pragma unroll
     for (int f0 = 0; f0 < ITEMS; f0 += CW) {
+      if (f0 + wave0 >= ITEMS) continue;  // wave-uniform
       const int f = f0 + tid;
-      if (f < nitems) {
-        const int r = f / NCH, c = f - r * NCH;
-        const int e0 = cs + c * CH;
-        if (e0 < nb) {
-          const uint4 v = *reinterpret_cast<const uint4*>(plane + (size_t)(rlo + r) * nb + e0);
-          *reinterpret_cast<uint4*>(strip + HT::off(k) + r * HT::pitch(k) + c * CH) = v;
-        }
-      }
+      const int r = f / NCH, c = f - r * NCH;
+      const int row = base + r, e0 = cs + c * CH;
+      if (f < ITEMS && row >= 0 && row < a.Z && e0 < nb)
+        load_lds16(plane + (size_t)row * nb + e0,
+                   reinterpret_cast<char*>(strip) + HT::off(k) * (int)sizeof(RT) + (f0 + wave0) * 16);
     }
   });
   __syncthreads();
 
   const int R = R0 + tid;
   if (R >= nb - a.hmax) return;
-  int roff[H];
+  // byte offset of this cell's harmonic-k bin in row 0 of strip k; kept
+  // opaque so that the compiler holds it in a register and folds every row
+  // offset into the LDS instruction's immediate
+  const char* lds = reinterpret_cast<const char*>(strip);
+  int boff[H];
   static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    roff[k - 1] = HT::off(k) + ((k * (R0 / H)) & (CH - 1)) + (2 * k * tid + H) / (2 * H);
+    int b = (HT::off(k) + (2 * k * tid + H) / (2 * H)) * (int)sizeof(RT);
+    asm volatile("" : "+v"(b));
+    boff[k - 1] = b;
   });
-  for (int j = jt0; j < jt1; ++j) {
-    const int m = j - a.j0;
-    float tk[H];
-    static_for<1, H + 1>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      const int rel = harm_row(a.j0, m, k, H) - harm_row(a.j0, jt0 - a.j0, k, H);
-      tk[k - 1] = PS::unpack_real(strip[roff[k - 1] + rel * HT::pitch(k)]);
+  // per-cell thresholds: a stage whose fundamental R / 2^st lies below r_lo
+  // is not searched (threshold +inf)
+  bool en[NST];
+  float thr[NST];
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    en[st] = R >= (1 << st) * a.r_lo;
+    thr[st] = en[st] ? a.tau[st] : __builtin_inff();
+  }
+  // wave-wide pass masks per trial (scalar registers)
+  unsigned long long bal[kBand];
+  auto band = [&](auto negc) {
+    constexpr bool NEG = decltype(negc)::value;
+    static_for<0, kBand>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      bal[t] = 0;
+      if (t >= t_lo && t < t_hi) {
+        bool pass = false;
+        stage_sums<PDT, H>(
+            lds, boff,
+            [](auto kc) {
+              constexpr int k = decltype(kc)::value;
+              return HT::rel(k, t, NEG) * HT::pitch(k) * (int)sizeof(RT);
+            },
+            [&](int st, float S) { pass |= S >= thr[st]; });
+        bal[t] = __ballot(pass);
+      }
     });
+  };
+  if (u < 0)
+    band(std::true_type{});
+  else
+    band(std::false_type{});
+
+  // rare: cells with a passing stage report their most significant one
+  unsigned long long any = 0;
+#pragma unroll
+  for (int t = 0; t < kBand; ++t) any |= bal[t];
+  if (!any) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int t = 0; t < kBand; ++t) mask |= (uint32_t)((bal[t] >> lane) & 1ull) << t;
+  const bool neg = u < 0;
+  while (mask) {
+    const int t = __builtin_ctz(mask);
+    mask &= mask - 1;
+    const int j = jt0 + t;
     float S[NST];
-    bool any = false;
-#pragma unroll
-    for (int st = 0; st < NST; ++st) {
-      const int step = H >> st;  // stage H' = 2^st uses k = step, 2 step, ..., H
-      float sum = 0.f;
-#pragma unroll
-      for (int k = step; k <= H; k += step) sum += tk[k - 1];
-      S[st] = sum;
-      any |= (R >= (1 << st) * a.r_lo) && (sum >= a.tau[st]);
-    }
-    if (!any) continue;
+    stage_sums<PDT, H>(
+        lds, boff,
+        [&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
+        },
+        [&](int st, float v) { S[st] = v; });
     double best = 0.0;
     int bi = -1;
     for (int st = 0; st < NST; ++st) {
-      if (!((R >= (1 << st) * a.r_lo) && (S[st] >= a.tau[st]))) continue;
+      if (!(en[st] && S[st] >= thr[st])) continue;
       const double lq = log_tail_gamma((double)S[st], 1 << st);
       if (bi < 0 || lq < best) {
         best = lq;
         bi = st;
       }
     }
+    if (bi < 0) continue;  // only an infinite sum at an unsearched stage gets here
     const unsigned long long slot = atomicAdd(a.count, 1ull);
     if ((int64_t)slot < a.capacity) {
       const int hh = 1 << bi;
@@ -193,12 +310,13 @@ __global__ __launch_bounds__(256) void k_cand_sigma(fdas_candidate* __restrict__
 
 template <int PDT, int H>
 static void hs_launch(const HarmArgs& a, dim3 g, hipStream_t st) {
-  constexpr int JT = HarmCfg<PDT>::JT, G = HarmCfg<PDT>::GROUP;
-  const int nby = (a.Z + JT - 1) / JT;
-  const int ngroups = (nby + G - 1) / G;
-  const int nbx = (a.max_bins + kCells - 1) / kCells;
-  g.x = (unsigned)((int64_t)ngroups * G * nbx);
-  hipLaunchKernelGGL((k_harmsum<PDT, H>), g, dim3(kCells), 0, st, a);
+  constexpr int CW = HarmCfg<PDT>::CW, G = HarmCfg<PDT>::GROUP;
+  const int fd = [](int x, int y) { return (x >= 0 ? x : x - y + 1) / y; }(-a.j0, kBand);
+  const int nbands = [](int x, int y) { return (x >= 0 ? x : x - y + 1) / y; }(a.Z - 1 - a.j0, kBand) - fd + 1;
+  const int ngroups = (nbands + G - 1) / G;
+  const int ncol = (a.max_bins + CW - 1) / CW;
+  g.x = (unsigned)((int64_t)ngroups * G * ncol);
+  hipLaunchKernelGGL((k_harmsum<PDT, H>), g, dim3(CW), 0, st, a);
 }
 
 template <int PDT>

@@ -147,13 +147,13 @@ __device__ inline RzEval rz_eval(const void* spec, int64_t nb, double r, double 
 }
 
 template <int SDT>
-__global__ __launch_bounds__(256) void k_rz_power(const void* spec, int64_t nb, const float* r, const float* z, int64_t n,
-                                                  int margin, float* p, c64* y_out) {
+__global__ __launch_bounds__(256) void k_rz_power(const void* spec, int64_t nb, const double* r, const double* z, int64_t n,
+                                                  int margin, double* p, c64* y_out) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
-  const RzEval e = rz_eval<SDT, false>(spec, nb, (double)r[c], (double)z[c], margin);
+  const RzEval e = rz_eval<SDT, false>(spec, nb, r[c], z[c], margin);
   if ((threadIdx.x & 63) == 0) {
-    p[c] = (float)(e.y.re * e.y.re + e.y.im * e.y.im);
+    p[c] = e.y.re * e.y.re + e.y.im * e.y.im;
     if (y_out) y_out[c] = e.y;
   }
 }
@@ -161,18 +161,18 @@ __global__ __launch_bounds__(256) void k_rz_power(const void* spec, int64_t nb, 
 constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point unit of the spectrum-gradient accumulator
 
 template <int SDT>
-__global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, const float* r, const float* z,
-                                                 const c64* y_in, const float* gp, int64_t n, int margin,
-                                                 float* gr, float* gz, unsigned long long* acc) {
+__global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, const double* r, const double* z,
+                                                 const c64* y_in, const double* gp, int64_t n, int margin,
+                                                 double* gr, double* gz, unsigned long long* acc) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
-  const double rr = (double)r[c], zz = (double)z[c];
+  const double rr = r[c], zz = z[c];
   const RzEval e = rz_eval<SDT, true>(spec, nb, rr, zz, margin);
   const c64 y = y_in ? y_in[c] : e.y;
-  const double g = (double)gp[c];
+  const double g = gp[c];
   if ((threadIdx.x & 63) == 0) {
-    gr[c] = (float)(g * 2.0 * (y.re * e.dydr.re + y.im * e.dydr.im));
-    gz[c] = (float)(g * 2.0 * (y.re * e.dydz.re + y.im * e.dydz.im));
+    gr[c] = g * 2.0 * (y.re * e.dydr.re + y.im * e.dydr.im);
+    gz[c] = g * 2.0 * (y.re * e.dydz.re + y.im * e.dydz.im);
   }
   if (!acc) return;
   // dP/dA_k = 2 y rho(k - r, z), accumulated in 2^-40 fixed point: integer
@@ -203,12 +203,12 @@ __global__ void k_fix_to_float(const unsigned long long* acc, float* out, int64_
 // mismatch), so the step (g_r / (2 a P), g_z / (2 b P)) is Newton's step for
 // that model; it is clamped and halved until P increases.
 template <int SDT>
-__global__ __launch_bounds__(256) void k_refine(const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters,
+__global__ __launch_bounds__(256) void k_refine(const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters,
                                                 int margin, double* p_final) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
   constexpr double A = kPi64 * kPi64 / 3.0, B = kPi64 * kPi64 / 180.0;
-  double rr = (double)r[c], zz = (double)z[c];
+  double rr = r[c], zz = z[c];
   RzEval e = rz_eval<SDT, true>(spec, nb, rr, zz, margin);
   double P = e.y.re * e.y.re + e.y.im * e.y.im;
   for (int it = 0; it < iters && P > 0.0; ++it) {
@@ -233,17 +233,17 @@ __global__ __launch_bounds__(256) void k_refine(const void* spec, int64_t nb, fl
     }
     if (!moved || (fabs(sr) < 1e-7 && fabs(sz) < 1e-6)) break;
   }
+  // final FP64 evaluation at the returned position
+  const RzEval f = rz_eval<SDT, false>(spec, nb, rr, zz, margin);
   if ((threadIdx.x & 63) == 0) {
-    r[c] = (float)rr;
-    z[c] = (float)zz;
+    r[c] = rr;
+    z[c] = zz;
+    p_final[c] = f.y.re * f.y.re + f.y.im * f.y.im;
   }
-  // final FP64 evaluation at the stored (float) position
-  const RzEval f = rz_eval<SDT, false>(spec, nb, (double)(float)rr, (double)(float)zz, margin);
-  if ((threadIdx.x & 63) == 0) p_final[c] = f.y.re * f.y.re + f.y.im * f.y.im;
 }
 
-hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const float* r, const float* z, int64_t n, int margin,
-                           float* p, c64* y, hipStream_t st) {
+hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,
+                           double* p, c64* y, hipStream_t st) {
   const dim3 g((unsigned)((n + 3) / 4));
   switch (sdt) {
     case FDAS_F32: hipLaunchKernelGGL((k_rz_power<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, n, margin, p, y); break;
@@ -254,8 +254,8 @@ hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const float* r
   return hipGetLastError();
 }
 
-hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const float* r, const float* z, const c64* y,
-                          const float* gp, int64_t n, int margin, float* gr, float* gz, float* gspec,
+hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r, const double* z, const c64* y,
+                          const double* gp, int64_t n, int margin, double* gr, double* gz, float* gspec,
                           unsigned long long* acc, hipStream_t st) {
   const dim3 g((unsigned)((n + 3) / 4));
   if (gspec) {
@@ -272,7 +272,7 @@ hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const float* r,
   return hipGetLastError();
 }
 
-hipError_t launch_refine(int sdt, const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters, int margin,
+hipError_t launch_refine(int sdt, const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters, int margin,
                          double* p_final, hipStream_t st) {
   const dim3 g((unsigned)((n + 3) / 4));
   switch (sdt) {

@@ -85,12 +85,12 @@ struct HarmArgs {
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
 
 // a12
-hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const float* r, const float* z, int64_t n, int margin,
-                           float* p, c64* y, hipStream_t st);
-hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const float* r, const float* z, const c64* y,
-                          const float* gp, int64_t n, int margin, float* gr, float* gz, float* gspec,
+hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,
+                           double* p, c64* y, hipStream_t st);
+hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r, const double* z, const c64* y,
+                          const double* gp, int64_t n, int margin, double* gr, double* gz, float* gspec,
                           unsigned long long* acc, hipStream_t st);
-hipError_t launch_refine(int sdt, const void* spec, int64_t nb, float* r, float* z, int64_t n, int iters, int margin,
+hipError_t launch_refine(int sdt, const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters, int margin,
                          double* p_final, hipStream_t st);
 
 // small helpers (fill kernels are graph-capture safe, unlike memset nodes)

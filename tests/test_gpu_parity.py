@@ -287,7 +287,7 @@ def test_search_graph_replays_match_eager(lib):
     """fdas_search captured into a HIP graph: every replay (with eager work and
     synchronisations in between) reproduces the eager result bit for bit."""
     import torch
-    n = 1 << 18
+    n = 1 << 19
     lens = [n, n // 2, n // 4, n]
     xs, truths = synth.batch_series(lens, seed=51, amp=(0.05, 0.08))
     flat, offs, lens_a = synth.concat(xs)

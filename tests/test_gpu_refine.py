@@ -13,14 +13,23 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def setup(lib, n, n_truth, seed, store="f32"):
+def setup(lib, n, n_truth, seed, store="f32", small_z_first=False):
     truths, starts = synth.refine_candidates(seed, n_truth, r_gap=400.0)
+    if small_z_first:
+        t = truths[0]
+        truths[0] = synth.Injection(t.amp, t.r_mean - 0.005, 0.01, t.phase)
     xt = synth.make_series_device(n, truths, seed, 0)
     pl = lib.Plan(store=store, n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, make_templates=False)
     spec = pl.spectrum(xt, [0], [n])
     a = spec.float().cpu().numpy().astype(np.float64)
     a = a[:, 0] + 1j * a[:, 1]
     return pl, spec, a, truths, starts
+
+
+def smooth_in_z(z, h):
+    """True where z - h, z and z + h share the window half-width ceil(|z|/2)."""
+    c = np.ceil(np.abs(z) / 2)
+    return (np.ceil(np.abs(z + h) / 2) == c) & (np.ceil(np.abs(z - h) / 2) == c)
 
 
 def test_rz_power_and_y_match_oracle(lib):
@@ -31,16 +40,16 @@ def test_rz_power_and_y_match_oracle(lib):
     st = starts.copy()
     st[:4, 1] = [0.0, 1e-3, -0.02, 0.3]   # small-|z| branch and z = 0
     st[4:8, 0] = np.floor(st[4:8, 0])     # integer r
-    r = torch.tensor(st[:, 0], dtype=torch.float32, device="cuda")
-    z = torch.tensor(st[:, 1], dtype=torch.float32, device="cuda")
+    r = torch.tensor(st[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(st[:, 1], dtype=torch.float64, device="cuda")
     p, y = pl.rz_power(spec, r, z)
     p = p.cpu().numpy()
     y = y.cpu().numpy()
-    rf, zf = r.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64)
+    rf, zf = r.cpu().numpy(), z.cpu().numpy()
     for i in range(len(st)):
         yo = o.rz_amplitude(a, rf[i], zf[i])
         assert abs(y[i] - yo) <= 1e-9 * max(1.0, abs(yo)), (i, y[i], yo)
-        assert abs(p[i] - abs(yo) ** 2) <= 2e-6 * max(1.0, abs(yo) ** 2)
+        assert abs(p[i] - abs(yo) ** 2) <= 1e-9 * max(1.0, abs(yo) ** 2)
 
 
 def test_rz_gradients_match_oracle_and_differences(lib):
@@ -50,36 +59,40 @@ def test_rz_gradients_match_oracle_and_differences(lib):
     pl, spec, a, truths, starts = setup(lib, n, 48, 42)
     st = starts.copy()
     st[:3, 1] = [0.0, 2e-3, -0.04]
-    r = torch.tensor(st[:, 0], dtype=torch.float32, device="cuda")
-    z = torch.tensor(st[:, 1], dtype=torch.float32, device="cuda")
-    gp = torch.linspace(0.5, 2.0, len(st), device="cuda")
+    r = torch.tensor(st[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(st[:, 1], dtype=torch.float64, device="cuda")
+    gp = torch.linspace(0.5, 2.0, len(st), device="cuda", dtype=torch.float64)
     p, y = pl.rz_power(spec, r, z)
     gr, gz, gs = pl.rz_power_grad(spec, r, z, gp, y=y)
     gr2, gz2, gs2 = pl.rz_power_grad(spec, r, z, gp, y=y)
     assert torch.equal(gs, gs2) and torch.equal(gr, gr2)   # deterministic accumulation
     gr, gz, gs = gr.cpu().numpy(), gz.cpu().numpy(), gs.cpu().numpy().astype(np.complex128)
-    rf, zf = r.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64)
-    g = gp.cpu().numpy().astype(np.float64)
+    rf, zf = r.cpu().numpy(), z.cpu().numpy()
+    g = gp.cpu().numpy()
     want_gs = np.zeros(len(a), complex)
     for i in range(len(st)):
         P, dr, dz, ks, ga = o.rz_power_grad(a, rf[i], zf[i])
-        assert abs(gr[i] - g[i] * dr) <= 1e-5 * max(1.0, abs(g[i] * dr)), (i, gr[i], g[i] * dr)
-        assert abs(gz[i] - g[i] * dz) <= 1e-5 * max(1.0, abs(g[i] * dz)), (i, gz[i], g[i] * dz)
+        assert abs(gr[i] - g[i] * dr) <= 1e-8 * max(1.0, abs(g[i] * dr)), (i, gr[i], g[i] * dr)
+        assert abs(gz[i] - g[i] * dz) <= 1e-8 * max(1.0, abs(g[i] * dz)), (i, gz[i], g[i] * dz)
         want_gs[ks] += g[i] * ga
     np.testing.assert_allclose(gs, want_gs, rtol=0, atol=1e-5 * np.abs(want_gs).max())
     # central differences of the GPU's own forward, h = 1e-3
     h = 1e-3
     rr, zz = rf[:16], zf[:16]
     def P(rv, zv):
-        pp, _ = pl.rz_power(spec, torch.tensor(rv, dtype=torch.float32, device="cuda"),
-                            torch.tensor(zv, dtype=torch.float32, device="cuda"), keep_y=False)
+        pp, _ = pl.rz_power(spec, torch.tensor(rv, dtype=torch.float64, device="cuda"),
+                            torch.tensor(zv, dtype=torch.float64, device="cuda"), keep_y=False)
         return pp.cpu().numpy().astype(np.float64)
-    # float32 positions: step in exactly representable increments
     fr = (P(rr + h, zz) - P(rr - h, zz)) / (2 * h)
     fz = (P(rr, zz + h) - P(rr, zz - h)) / (2 * h)
     scale = np.maximum(1.0, P(rr, zz))
-    assert np.all(np.abs(gr[:16] / g[:16] - fr) <= 2e-2 * scale)
-    assert np.all(np.abs(gz[:16] / g[:16] - fz) <= 2e-2 * scale)
+    # P is piecewise smooth (window steps at integer r and even z): a central
+    # difference is taken only where both points lie in the same piece
+    okr = np.floor(rr + h) == np.floor(rr - h)
+    assert np.all((np.abs(gr[:16] / g[:16] - fr) <= 1e-4 * scale)[okr])
+    ok = smooth_in_z(zz, h)
+    assert ok.sum() >= 14 and okr.sum() >= 14
+    assert np.all((np.abs(gz[:16] / g[:16] - fz) <= 1e-4 * scale)[ok])
 
 
 def test_autograd_function(lib):
@@ -91,11 +104,11 @@ def test_autograd_function(lib):
     pl = lib.Plan(n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, make_templates=False)
     spec = pl.spectrum(torch.from_numpy(x).to("cuda"), [0], [n])
     sc = torch.view_as_complex(spec.clone()).requires_grad_(True)
-    r = torch.tensor(starts[:, 0], dtype=torch.float32, device="cuda", requires_grad=True)
-    z = torch.tensor(starts[:, 1], dtype=torch.float32, device="cuda", requires_grad=True)
+    r = torch.tensor(starts[:, 0], dtype=torch.float64, device="cuda", requires_grad=True)
+    z = torch.tensor(starts[:, 1], dtype=torch.float64, device="cuda", requires_grad=True)
     p = lib.rz_power(sc, r, z, pl)
     (p * torch.arange(1, 9, device="cuda")).sum().backward()
-    gr, gz, gs = pl.rz_power_grad(spec, r.detach(), z.detach(), torch.arange(1, 9, device="cuda").float())
+    gr, gz, gs = pl.rz_power_grad(spec, r.detach(), z.detach(), torch.arange(1, 9, device="cuda").double())
     assert torch.allclose(r.grad, gr) and torch.allclose(z.grad, gz)
     assert torch.equal(sc.grad, gs)
 
@@ -105,13 +118,13 @@ def test_refine_reaches_oracle_optimum(lib, store):
     import torch
     n = 1 << 18
     say("fdas_refine", n, store)
-    pl, spec, a, truths, starts = setup(lib, n, 12, 44, store=store)
+    pl, spec, a, truths, starts = setup(lib, n, 12, 44, store=store, small_z_first=True)
     st = starts.copy()
-    st[0] = (truths[0].r_mean + 0.3, 0.02)           # near-zero drift start
-    r = torch.tensor(st[:, 0], dtype=torch.float32, device="cuda")
-    z = torch.tensor(st[:, 1], dtype=torch.float32, device="cuda")
+    st[0] = (truths[0].r_mean + 0.3, 0.02)           # near-zero drift start (truth z = 0.01)
+    r = torch.tensor(st[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(st[:, 1], dtype=torch.float64, device="cuda")
     rr, zz, pf = pl.refine(spec, r, z, n_iter=40)
-    rr, zz, pf = rr.cpu().numpy().astype(np.float64), zz.cpu().numpy().astype(np.float64), pf.cpu().numpy()
+    rr, zz, pf = rr.cpu().numpy(), zz.cpu().numpy(), pf.cpu().numpy()
     for i in range(len(st)):
         ro, zo, po = o.refine_optimum(a, st[i, 0], st[i, 1])
         # the FP64 final power is the oracle's P at the returned position
@@ -127,22 +140,38 @@ def test_refine_full_size_sampled(lib):
     n = 1 << 22
     say("fdas_refine full size", n)
     pl, spec, a, truths, starts = setup(lib, n, 4096, 4)
-    r = torch.tensor(starts[:, 0], dtype=torch.float32, device="cuda")
-    z = torch.tensor(starts[:, 1], dtype=torch.float32, device="cuda")
-    gp = torch.ones(4096, device="cuda")
+    r = torch.tensor(starts[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(starts[:, 1], dtype=torch.float64, device="cuda")
+    gp = torch.ones(4096, device="cuda", dtype=torch.float64)
     p, y = pl.rz_power(spec, r, z)
     gr, gz, _ = pl.rz_power_grad(spec, r, z, gp, y=y, want_spectrum=False)
     rr, zz, pf = pl.refine(spec, r, z, n_iter=40)
     sel = np.random.default_rng(0).choice(4096, 64, replace=False)
-    rf, zf = r.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64)
+    rf, zf = r.cpu().numpy(), z.cpu().numpy()
     gr, gz = gr.cpu().numpy(), gz.cpu().numpy()
-    rr, zz, pf = rr.cpu().numpy().astype(np.float64), zz.cpu().numpy().astype(np.float64), pf.cpu().numpy()
+    rr, zz, pf = rr.cpu().numpy(), zz.cpu().numpy(), pf.cpu().numpy()
     for i in sel[:64]:
         P, dr, dz, _, _ = o.rz_power_grad(a, rf[i], zf[i])
-        assert abs(gr[i] - dr) <= 1e-5 * max(1.0, abs(dr)) and abs(gz[i] - dz) <= 1e-5 * max(1.0, abs(dz))
+        assert abs(gr[i] - dr) <= 1e-8 * max(1.0, abs(dr)) and abs(gz[i] - dz) <= 1e-8 * max(1.0, abs(dz))
+        # central differences, h = 1e-3, of the GPU's own forward
+        h = 1e-3
+        rp = torch.tensor([rf[i] + h, rf[i] - h, rf[i], rf[i]], dtype=torch.float64, device="cuda")
+        zp = torch.tensor([zf[i], zf[i], zf[i] + h, zf[i] - h], dtype=torch.float64, device="cuda")
+        pp, _ = pl.rz_power(spec, rp, zp, keep_y=False)
+        pp = pp.cpu().numpy()
+        if np.floor(rf[i] + h) == np.floor(rf[i] - h):
+            assert abs((pp[0] - pp[1]) / (2 * h) - gr[i]) <= 1e-4 * max(1.0, P)
+        if smooth_in_z(zf[i], h):
+            assert abs((pp[2] - pp[3]) / (2 * h) - gz[i]) <= 1e-4 * max(1.0, P)
     for i in sel[:16]:
         ro, zo, po = o.refine_optimum(a, rf[i], zf[i])
-        assert abs(pf[i] - po) <= 1e-3 * po and abs(rr[i] - ro) <= 0.02 and abs(zz[i] - zo) <= 0.1, i
+        assert abs(pf[i] - po) <= 1e-3 * po and abs(rr[i] - ro) <= 0.02, i
+        # The window half-width m + ceil(|z|/2) steps at even z, so P is
+        # piecewise smooth: ascent may stop at the maximum of the piece next
+        # to the oracle's (grid search sees across the step).  Then the two
+        # agree in P (above) but z may differ by up to the step's reach.
+        same_piece = np.ceil(abs(zz[i]) / 2) == np.ceil(abs(zo) / 2)
+        assert abs(zz[i] - zo) <= (0.1 if same_piece else 0.5), (i, zz[i], zo)
     # every truth's refined position lies within a bin and 1 z of it
     tr = np.array([t.r_mean for t in truths])
     tz = np.array([t.z for t in truths])
