@@ -61,7 +61,9 @@ constexpr int kBand = 16;
 template <int H, int CW, int CH>
 struct HarmTile {
   static constexpr int rows(int k) { return (2 * k * (kBand - 1) + H) / (2 * H) + 1; }
-  static constexpr int chunks(int k) { return (CW * k / H + 1 + CH - 1) / CH; }  // 16-byte chunks per strip row
+  // bins of harmonic k read by the tile: 0 .. floor((2k(CW-1) + H)/(2H))
+  static constexpr int span(int k) { return (2 * k * (CW - 1) + H) / (2 * H) + 1; }
+  static constexpr int chunks(int k) { return (span(k) + CH - 1) / CH; }          // 16-byte chunks per strip row
   static constexpr int pitch(int k) { return chunks(k) * CH; }                     // elements per strip row
   static constexpr int off(int k) { return k <= 1 ? 0 : off(k - 1) + rows(k - 1) * pitch(k - 1); }
   static constexpr int SIZE = off(H + 1);                                           // elements of LDS
@@ -81,6 +83,18 @@ struct HarmCfg {
   // plane reads from HBM, against ~4 when every column tile walks all bands).
   static constexpr int GROUP = 3;
 };
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b to XCD b % 8).
+// The launch order is remapped so that each XCD takes runs of kXcdRun
+// consecutive tiles (neighbouring columns, whose strips share their edge
+// cache lines in that XCD's L2) while all XCDs advance through one common
+// front of the tile sequence.
+constexpr int kXcds = 8, kXcdRun = 16;
+__device__ __forceinline__ int xcd_tile(int b) {
+  constexpr int W = kXcds * kXcdRun;
+  const int r = b % W;
+  return b - r + (r % kXcds) * kXcdRun + r / kXcds;
+}
 
 __device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0 ? a : a - b + 1) / b; }
 
@@ -167,7 +181,8 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   const SeriesDesc d = a.desc[blockIdx.z];
   const int nb = d.nbins;
   const int ncol = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
-  const int grp = blockIdx.x / (ncol * G), inner = blockIdx.x % (ncol * G);
+  const int tile = xcd_tile(blockIdx.x);
+  const int grp = tile / (ncol * G), inner = tile % (ncol * G);
   const int R0 = (inner / G) * CW;
   const int u = floordiv(-a.j0, kBand) + grp * G + inner % G;
   const int jt0 = a.j0 + kBand * u;  // trial of t = 0
@@ -315,7 +330,8 @@ static void hs_launch(const HarmArgs& a, dim3 g, hipStream_t st) {
   const int nbands = [](int x, int y) { return (x >= 0 ? x : x - y + 1) / y; }(a.Z - 1 - a.j0, kBand) - fd + 1;
   const int ngroups = (nbands + G - 1) / G;
   const int ncol = (a.max_bins + CW - 1) / CW;
-  g.x = (unsigned)((int64_t)ngroups * G * ncol);
+  constexpr int W = kXcds * kXcdRun;
+  g.x = (unsigned)(((int64_t)ngroups * G * ncol + W - 1) / W * W);  // tiles past the last group exit
   hipLaunchKernelGGL((k_harmsum<PDT, H>), g, dim3(CW), 0, st, a);
 }
 
