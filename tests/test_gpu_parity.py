@@ -257,6 +257,58 @@ def test_harmonic_sum_candidates_match_oracle(lib):
         assert abs(k["sigma"] - o.gaussian_sigma(float(k["power"]), int(k["harm"]))) < 1e-3 * k["sigma"]
 
 
+@pytest.mark.parametrize("plane_dt", ["bf16", "f32"])
+def test_harmonic_sum_16_ragged_batch_matches_oracle(lib, plane_dt):
+    """Harmonic sums to 16 over a ragged batch (2^18 and 2^17 samples, 97
+    trials: bands on both sides of z = 0 and a one-trial edge band), against
+    the oracle's sums of the GPU's own plane: the candidate cells, their
+    stage and their power agree except where a sum lies within 1e-5 of a
+    threshold (FP32 against FP64 accumulation)."""
+    import torch
+    n = 1 << 18
+    lens = [n, n // 2, n, n // 2]
+    xs, truths = synth.batch_series(lens, seed=61, inj_per_series=(1, 2), amp=(0.04, 0.07), z_abs=44.0)
+    x, offs, _ = synth.concat(xs)
+    say("fdas_harmonic_sum H=16 ragged batch", plane_dt)
+    pl = lib.Plan(store=plane_dt, plane=plane_dt, n_samples=n, max_batch_samples=sum(lens), z_min=-48.0,
+                  z_max=48.0, z_step=1.0, n_harmonics=16, segment_len=1024)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), offs, lens)
+    cap = 1 << 22
+    cands, count = pl.harmonic_sum(P, lens, capacity=cap)
+    pl.check(count, cap)
+    c = lib.candidates_to_numpy(cands, int(count.item()))
+    zs = o.z_grid(-48, 48, 1)
+    j0 = int(np.argmin(np.abs(zs)))
+    tau = {H: o.threshold(H) for H in (1, 2, 4, 8, 16)}
+    Pall = P.float().cpu().numpy().astype(np.float64)
+    off = 0
+    n_cells = 0
+    for s_, L_ in enumerate(lens):
+        nb = L_ // 2
+        plane = Pall[off: off + pl.Z * nb].reshape(pl.Z, nb)
+        off += pl.Z * nb
+        sums = o.harmonic_sums(plane, j0, 16)
+        want = {(k.R, k.j): k for k in o.search(plane, zs, 16, r_lo=pl.hmax, h_max=pl.hmax)}
+        mine = c[c["series"] == s_]
+        got = {(int(k["R"]), int(k["j"])): k for k in mine}
+        assert len(got) == len(mine)  # one record per cell
+
+        def borderline(R, j):
+            return any(abs(sums[H][j, R] - tau[H]) <= 1e-5 * tau[H] for H in tau)
+
+        for cell in set(got) ^ set(want):
+            assert borderline(*cell), (s_, cell)
+        for cell in set(got) & set(want):
+            g, w = got[cell], want[cell]
+            if int(g["harm"]) != w.harm:
+                assert borderline(*cell), (s_, cell, int(g["harm"]), w.harm)
+                continue
+            assert abs(float(g["power"]) - w.power) <= 1e-5 * w.power, (s_, cell)
+        assert len(want) >= 20, (s_, len(want))
+        n_cells += len(want)
+    assert n_cells == len(c) or abs(n_cells - len(c)) <= 0.001 * n_cells
+
+
 def test_candidate_overflow_is_reported(lib):
     n = 1 << 17
     x = synth.make_series(n, [synth.Injection(0.1, 3000.0, 8.0, 0.1)], 8, 0)
