@@ -101,43 +101,51 @@ __device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0 ? a : a -
 // Nested stage sums: stage 0 is harmonic H alone; stage st adds the odd
 // multiples of H / 2^st, so the sum handed to sink(st, S) covers
 // k = H/2^st, 2 H/2^st, ..., H.
-// The harmonic values are read from LDS at byte offsets boff[k-1] + OFF(k).
 //  * FP32 planes: plain FP32 additions in that order.
 //  * 16-bit planes: the values are read in pairs into one register (stage 1
 //    pairs H with H/2; later stages pair consecutive odd multiples) and each
 //    pair is added to the running sum by one FP32-accumulating two-term dot
 //    product with (1, 1), the products being exact.
-template <int PDT>
-__device__ __forceinline__ uint32_t lds_u16(const char* lds, int boff) {
-  return *reinterpret_cast<const uint16_t*>(lds + boff);
+// The H values of one cell, as read from LDS (16-bit planes: the raw bits,
+// zero-extended; FP32 planes: the float bits).
+template <int H>
+struct HarmVals {
+  uint32_t v[H];
+};
+
+template <int PDT, int H, typename OFF>
+__device__ __forceinline__ HarmVals<H> load_vals(const char* lds, const int* boff, OFF off) {
+  HarmVals<H> r;
+  static_for<1, H + 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const char* p = lds + boff[k - 1] + off(kc);
+    if constexpr (Store<PDT>::RBYTES == 4)
+      r.v[k - 1] = *reinterpret_cast<const uint32_t*>(p);
+    else
+      r.v[k - 1] = *reinterpret_cast<const uint16_t*>(p);
+  });
+  return r;
 }
 
-template <int PDT, int H, typename OFF, typename SINK>
-__device__ __forceinline__ void stage_sums(const char* lds, const int* boff, OFF off, SINK sink) {
+template <int PDT, int H, typename SINK>
+__device__ __forceinline__ void stage_sums(const HarmVals<H>& x, SINK sink) {
   using PS = Store<PDT>;
   using RT = typename PS::real_t;
   constexpr int NST = ilog2(H) + 1;
-  auto at = [&](auto kc) -> const char* { return lds + boff[decltype(kc)::value - 1] + off(kc); };
   if constexpr (PS::RBYTES == 4) {
-    float s = *reinterpret_cast<const float*>(at(std::integral_constant<int, H>{}));
+    float s = __uint_as_float(x.v[H - 1]);
     sink(0, s);
     static_for<1, NST>([&](auto sc) {
       constexpr int st = decltype(sc)::value;
       constexpr int step = H >> st;
       static_for<0, (1 << st) / 2>([&](auto ic) {
         constexpr int k = step * (2 * decltype(ic)::value + 1);
-        s += *reinterpret_cast<const float*>(at(std::integral_constant<int, k>{}));
+        s += __uint_as_float(x.v[k - 1]);
       });
       sink(st, s);
     });
   } else {
-    typedef unsigned short us2 __attribute__((ext_vector_type(2)));
-    auto pair = [&](auto ka, auto kb) {
-      us2 v;
-      v.x = *reinterpret_cast<const uint16_t*>(at(ka));
-      v.y = *reinterpret_cast<const uint16_t*>(at(kb));
-      return __builtin_bit_cast(uint32_t, v);
-    };
+    auto pair = [&](int ka, int kb) { return x.v[ka - 1] | (x.v[kb - 1] << 16); };
     auto dot = [](uint32_t w, float acc) {
       if constexpr (PDT == FDAS_BF16) {
         typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
@@ -149,9 +157,9 @@ __device__ __forceinline__ void stage_sums(const char* lds, const int* boff, OFF
       }
     };
     if constexpr (H == 1) {
-      sink(0, PS::unpack_real((RT)lds_u16<PDT>(lds, boff[0] + off(std::integral_constant<int, 1>{}))));
+      sink(0, PS::unpack_real((RT)x.v[0]));
     } else {
-      const uint32_t w1 = pair(std::integral_constant<int, H / 2>{}, std::integral_constant<int, H>{});
+      const uint32_t w1 = pair(H / 2, H);
       sink(0, PS::unpack_real((RT)(w1 >> 16)));
       float s = dot(w1, 0.f);
       sink(1, s);
@@ -160,7 +168,7 @@ __device__ __forceinline__ void stage_sums(const char* lds, const int* boff, OFF
         constexpr int step = H >> st;
         static_for<0, (1 << st) / 4>([&](auto ic) {
           constexpr int ka = step * (4 * decltype(ic)::value + 1), kb = ka + 2 * step;
-          s = dot(pair(std::integral_constant<int, ka>{}, std::integral_constant<int, kb>{}), s);
+          s = dot(pair(ka, kb), s);
         });
         sink(st, s);
       });
@@ -241,20 +249,26 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   unsigned long long bal[kBand];
   auto band = [&](auto negc) {
     constexpr bool NEG = decltype(negc)::value;
+    auto offs = [](auto tc) {
+      return [](auto kc) {
+        constexpr int k = decltype(kc)::value, t = decltype(tc)::value;
+        return HT::rel(k, t, NEG) * HT::pitch(k) * (int)sizeof(RT);
+      };
+    };
+    // software pipeline: the LDS reads of trial t + 1 are issued before the
+    // sums of trial t (every trial's reads stay inside the strips)
+    HarmVals<H> cur = load_vals<PDT, H>(lds, boff, offs(std::integral_constant<int, 0>{}));
     static_for<0, kBand>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
+      HarmVals<H> nxt;
+      if constexpr (t + 1 < kBand) nxt = load_vals<PDT, H>(lds, boff, offs(std::integral_constant<int, t + 1>{}));
       bal[t] = 0;
       if (t >= t_lo && t < t_hi) {
         bool pass = false;
-        stage_sums<PDT, H>(
-            lds, boff,
-            [](auto kc) {
-              constexpr int k = decltype(kc)::value;
-              return HT::rel(k, t, NEG) * HT::pitch(k) * (int)sizeof(RT);
-            },
-            [&](int st, float S) { pass |= S >= thr[st]; });
+        stage_sums<PDT, H>(cur, [&](int st, float S) { pass |= S >= thr[st]; });
         bal[t] = __ballot(pass);
       }
+      if constexpr (t + 1 < kBand) cur = nxt;
     });
   };
   if (u < 0)
@@ -277,13 +291,11 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     mask &= mask - 1;
     const int j = jt0 + t;
     float S[NST];
-    stage_sums<PDT, H>(
-        lds, boff,
-        [&](auto kc) {
-          constexpr int k = decltype(kc)::value;
-          return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
-        },
-        [&](int st, float v) { S[st] = v; });
+    const HarmVals<H> x = load_vals<PDT, H>(lds, boff, [&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
+    });
+    stage_sums<PDT, H>(x, [&](int st, float v) { S[st] = v; });
     double best = 0.0;
     int bi = -1;
     for (int st = 0; st < NST; ++st) {
