@@ -174,6 +174,24 @@ def batch_injections(lengths: Sequence[int], seed: int, inj_per_series=(0, 2), a
     return truths
 
 
+def ska_full(seed: int = 5, n: int = 1 << 23, counts=(3050, 1500, 1375), frac: float = 0.01,
+             amp=(0.01, 0.05), z_abs=96.0):
+    """The full SKA-like run: 5925 DM trials (3050 at N, 1500 at N/2 and 1375
+    at N/4 samples); a seeded 1 % of them (59) carry one injection each, with
+    amplitude U[0.01, 0.05] scaled by sqrt(decimation) and z in U[-96, 96].
+    Returns (lengths, injections per trial)."""
+    lens = [n] * counts[0] + [n // 2] * counts[1] + [n // 4] * counts[2]
+    rng = rng_for(seed, 50_000)
+    chosen = rng.choice(len(lens), int(round(frac * len(lens))), replace=False)
+    truths: List[List[Injection]] = [[] for _ in lens]
+    for i in sorted(int(c) for c in chosen):
+        inj = draw_injections(rng_for(seed, 50_001 + i), 1, lens[i], amp=amp, z_abs=z_abs)
+        for j in inj:
+            j.amp *= math.sqrt(n // lens[i])
+        truths[i] = inj
+    return lens, truths
+
+
 def fill_series_device(out, injections: Sequence[Injection], cfg_seed: int, series_index: int):
     """Large-batch variant of make_series for benchmarks: the N(0,1) noise comes
     from torch's device generator seeded with (cfg_seed, series_index) instead

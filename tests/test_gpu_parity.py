@@ -257,7 +257,7 @@ def test_harmonic_sum_candidates_match_oracle(lib):
         assert abs(k["sigma"] - o.gaussian_sigma(float(k["power"]), int(k["harm"]))) < 1e-3 * k["sigma"]
 
 
-@pytest.mark.parametrize("plane_dt", ["bf16", "f32"])
+@pytest.mark.parametrize("plane_dt", ["bf16", "f16", "f32"])
 def test_harmonic_sum_16_ragged_batch_matches_oracle(lib, plane_dt):
     """Harmonic sums to 16 over a ragged batch (2^18 and 2^17 samples, 97
     trials: bands on both sides of z = 0 and a one-trial edge band), against
