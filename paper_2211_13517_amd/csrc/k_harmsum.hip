@@ -53,20 +53,24 @@ __device__ inline double sigma_from_log_tail(double lq) {
 // with rel_k(t) = floor((2kt + H)/(2H)) for u >= 0 and ceil((2kt - H)/(2H))
 // for u < 0: a compile-time pattern.  Likewise harmonic k of cell R0 + i
 // reads bin k R0 / H + floor((2ki + H)/(2H)).  The block copies, for every
-// k, the rows base_k .. base_k + rows(k) - 1 of the bin strip it needs into
-// LDS with aligned 16-byte loads, synchronises once, and then evaluates its
-// CW x 16 cells with LDS reads whose offsets are all immediates.
+// k below the top two, the rows base_k .. base_k + rows(k) - 1 of the bin
+// strip it needs into LDS with aligned 16-byte loads, synchronises once, and
+// then evaluates its CW x 16 cells with LDS reads whose offsets are all
+// immediates.  The top two harmonics use (nearly) one value per cell, so
+// each thread loads those straight into registers; that keeps a tile's LDS
+// at 34 KB (four blocks per CU instead of three).
 constexpr int kBand = 16;
 
-template <int H, int CW, int CH>
+template <int H, int CW, int CH, int ND>
 struct HarmTile {
+  static constexpr int KL = H - ND;  // harmonics staged in LDS (the top ND are read directly)
   static constexpr int rows(int k) { return (2 * k * (kBand - 1) + H) / (2 * H) + 1; }
   // bins of harmonic k read by the tile: 0 .. floor((2k(CW-1) + H)/(2H))
   static constexpr int span(int k) { return (2 * k * (CW - 1) + H) / (2 * H) + 1; }
   static constexpr int chunks(int k) { return (span(k) + CH - 1) / CH; }          // 16-byte chunks per strip row
   static constexpr int pitch(int k) { return chunks(k) * CH; }                     // elements per strip row
   static constexpr int off(int k) { return k <= 1 ? 0 : off(k - 1) + rows(k - 1) * pitch(k - 1); }
-  static constexpr int SIZE = off(H + 1);                                           // elements of LDS
+  static constexpr int SIZE = off(KL + 1);                                          // elements of LDS
   // strip row of harmonic k for trial t of a band below (neg) or above z = 0
   static constexpr int rel(int k, int t, bool neg) {
     return neg ? (2 * k * t - H <= 0 ? 0 : (2 * k * t - H + 2 * H - 1) / (2 * H)) : (2 * k * t + H) / (2 * H);
@@ -113,16 +117,20 @@ struct HarmVals {
   uint32_t v[H];
 };
 
-template <int PDT, int H, typename OFF>
-__device__ __forceinline__ HarmVals<H> load_vals(const char* lds, const int* boff, OFF off) {
+template <int PDT, int H, int KL, typename OFF, typename DIR>
+__device__ __forceinline__ HarmVals<H> load_vals(const char* lds, const int* boff, OFF off, DIR dir) {
   HarmVals<H> r;
   static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const char* p = lds + boff[k - 1] + off(kc);
-    if constexpr (Store<PDT>::RBYTES == 4)
-      r.v[k - 1] = *reinterpret_cast<const uint32_t*>(p);
-    else
-      r.v[k - 1] = *reinterpret_cast<const uint16_t*>(p);
+    if constexpr (k > KL) {
+      r.v[k - 1] = dir(kc);
+    } else {
+      const char* p = lds + boff[k - 1] + off(kc);
+      if constexpr (Store<PDT>::RBYTES == 4)
+        r.v[k - 1] = *reinterpret_cast<const uint32_t*>(p);
+      else
+        r.v[k - 1] = *reinterpret_cast<const uint16_t*>(p);
+    }
   });
   return r;
 }
@@ -183,7 +191,10 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   constexpr int NST = ilog2(H) + 1;
   constexpr int CH = 16 / (int)sizeof(RT);
   constexpr int CW = HarmCfg<PDT>::CW, G = HarmCfg<PDT>::GROUP;
-  using HT = HarmTile<H, CW, CH>;
+  // The top ND harmonics read (nearly) one value per cell: they bypass LDS
+  // and are loaded by each thread straight into registers.
+  constexpr int ND = H >= 4 ? 2 : 0;
+  using HT = HarmTile<H, CW, CH, ND>;
   __shared__ __align__(16) RT strip[HT::SIZE];
 
   const SeriesDesc d = a.desc[blockIdx.z];
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   // base, and every load of the block is in flight before the one wait at
   // the barrier.  Rows outside the plane are never read by a valid trial.
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
-  static_for<1, H + 1>([&](auto kc) {
+  static_for<1, HT::KL + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
     const int base = a.j0 + (kBand / H) * k * u;
@@ -221,6 +232,36 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
                    reinterpret_cast<char*>(strip) + HT::off(k) * (int)sizeof(RT) + (f0 + wave0) * 16);
     }
   });
+  // The directly read harmonics: this thread's bin of each of their rows
+  // (rows outside the plane and bins past the series are clamped: their
+  // values only reach cells that are not searched).
+  auto raw = [](const RT* p) -> uint32_t {
+    if constexpr (sizeof(RT) == 4)
+      return *reinterpret_cast<const uint32_t*>(p);
+    else
+      return *reinterpret_cast<const uint16_t*>(p);
+  };
+  auto direct_ptr = [&](int k, int rel) {
+    const int cs = k * (R0 / H);
+    const int row = min(max(a.j0 + (kBand / H) * k * u + rel, 0), a.Z - 1);
+    const int pos = min((2 * k * tid + H) / (2 * H), nb - 1 - cs);
+    return plane + (size_t)row * nb + cs + pos;
+  };
+  uint32_t dv[ND > 0 ? ND : 1][kBand];
+  auto dload = [&](auto negc) {
+    constexpr bool NEG = decltype(negc)::value;
+    static_for<0, ND>([&](auto dc) {
+      constexpr int k = H - decltype(dc)::value;
+      static_for<0, kBand>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        dv[decltype(dc)::value][t] = raw(direct_ptr(k, HT::rel(k, t, NEG)));
+      });
+    });
+  };
+  if (u < 0)
+    dload(std::true_type{});
+  else
+    dload(std::false_type{});
   __syncthreads();
 
   const int R = R0 + tid;
@@ -230,7 +271,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   // offset into the LDS instruction's immediate
   const char* lds = reinterpret_cast<const char*>(strip);
   int boff[H];
-  static_for<1, H + 1>([&](auto kc) {
+  static_for<1, HT::KL + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     int b = (HT::off(k) + (2 * k * tid + H) / (2 * H)) * (int)sizeof(RT);
     asm volatile("" : "+v"(b));
@@ -257,11 +298,17 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     };
     // software pipeline: the LDS reads of trial t + 1 are issued before the
     // sums of trial t (every trial's reads stay inside the strips)
-    HarmVals<H> cur = load_vals<PDT, H>(lds, boff, offs(std::integral_constant<int, 0>{}));
+    auto dir = [&](auto tc) {
+      return [&](auto kc) { return dv[H - decltype(kc)::value][decltype(tc)::value]; };
+    };
+    HarmVals<H> cur = load_vals<PDT, H, HT::KL>(lds, boff, offs(std::integral_constant<int, 0>{}),
+                                               dir(std::integral_constant<int, 0>{}));
     static_for<0, kBand>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       HarmVals<H> nxt;
-      if constexpr (t + 1 < kBand) nxt = load_vals<PDT, H>(lds, boff, offs(std::integral_constant<int, t + 1>{}));
+      if constexpr (t + 1 < kBand)
+        nxt = load_vals<PDT, H, HT::KL>(lds, boff, offs(std::integral_constant<int, t + 1>{}),
+                                        dir(std::integral_constant<int, t + 1>{}));
       bal[t] = 0;
       if (t >= t_lo && t < t_hi) {
         bool pass = false;
@@ -291,10 +338,16 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     mask &= mask - 1;
     const int j = jt0 + t;
     float S[NST];
-    const HarmVals<H> x = load_vals<PDT, H>(lds, boff, [&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
-    });
+    const HarmVals<H> x = load_vals<PDT, H, HT::KL>(
+        lds, boff,
+        [&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
+        },
+        [&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          return raw(direct_ptr(k, HT::rel(k, t, neg)));
+        });
     stage_sums<PDT, H>(x, [&](int st, float v) { S[st] = v; });
     double best = 0.0;
     int bi = -1;
