@@ -80,14 +80,15 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
       v[c] = cmul(F[c], SS::unpack(tc[c]));
     });
     fft_run<FS, 1, BLOCK>(v, xb, tw, tid);
-    RT* row = out + (size_t)t * (uint32_t)d.nbins;
-    const uint32_t ooff = (uint32_t)(r0 + tid) * sizeof(RT);
+    // this thread's output i = tid + NT c lands at bin r0 + i of row t: one
+    // 64-bit pointer per template, the register index as an immediate offset
+    RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + tid);
     static_for<0, P>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       // the register is out of range for every thread: skip (uniform branch)
       if (NT * c + NT - 1 < lo || NT * c >= hi) return;
       const int i = tid + NT * c;
-      if (i >= lo && i < hi) st_off<RT>(row, ooff + c * NT * sizeof(RT), PS::pack_real(cnorm(v[c])));
+      if (i >= lo && i < hi) dst[NT * c] = PS::pack_real(cnorm(v[c]));
     });
     static_for<0, P>([&](auto cc) { tc[decltype(cc)::value] = tn[decltype(cc)::value]; });
   }
