@@ -372,6 +372,30 @@ def harmonic_sums(plane: np.ndarray, j0: int, n_harm: int) -> Dict[int, np.ndarr
     return out
 
 
+def harmonic_sum_cells(plane: np.ndarray, j0: int, n_harm: int, rows: np.ndarray, cols: np.ndarray
+                       ) -> Dict[int, np.ndarray]:
+    """S_H at the cells (rows[i], cols[i]) only, for H = 1, 2, ..., n_harm: the
+    same terms as harmonic_sums (harmonic k of the top stage at bin
+    round_half_up(k R / n_harm) and trial j0 + sgn(m) round_half_up(k |m| / n_harm)),
+    for planes too large to sum whole."""
+    R = np.asarray(cols, dtype=np.int64)
+    m = np.asarray(rows, dtype=np.int64) - j0
+    H = n_harm
+    terms = []
+    for k in range(1, H + 1):
+        rk = (2 * k * R + H) // (2 * H)
+        mk = np.sign(m) * ((2 * k * np.abs(m) + H) // (2 * H))
+        terms.append(plane[j0 + mk, rk].astype(np.float64))
+    terms = np.stack(terms)                                      # [k][cell]
+    out = {}
+    h = 1
+    while h <= H:
+        step = H // h
+        out[h] = terms[step - 1::step].sum(axis=0)
+        h *= 2
+    return out
+
+
 def stages(n_harm: int) -> List[int]:
     return [1 << i for i in range(int(math.log2(n_harm)) + 1)]
 
@@ -416,6 +440,28 @@ class Candidate:
     sigma: float
 
 
+def best_stage(sums: Dict[int, np.ndarray], R: np.ndarray, n_bins: int, r_lo: int, h_max: int,
+               sigma: float = 6.0):
+    """The stage a cell reports: among the stages H searched at bin R
+    (R >= H r_lo and R < n_bins - h_max) whose sum passes (S_H >= tau_H), the one
+    with the smallest noise tail probability.  Works elementwise on arrays of
+    sums (whole planes or lists of cells); returns (H or 0, ln tail)."""
+    shape = next(iter(sums.values())).shape
+    best_lq = np.full(shape, np.inf)
+    best_h = np.zeros(shape, dtype=np.int64)
+    for H, S in sums.items():
+        tau = threshold(H, sigma)
+        ok = (S >= tau) & (R >= H * r_lo) & (R < n_bins - h_max)
+        if not np.any(ok):
+            continue
+        lq = np.full(shape, np.inf)
+        lq[ok] = log_tail_gamma(S[ok], H)
+        better = lq < best_lq
+        best_lq = np.where(better, lq, best_lq)
+        best_h = np.where(better, H, best_h)
+    return best_h, best_lq
+
+
 def search(plane: np.ndarray, zs: np.ndarray, n_harm: int, r_lo: int, h_max: int,
            sigma: float = 6.0, series: int = 0) -> List[Candidate]:
     """Threshold the harmonic sums and emit at most one candidate per cell.
@@ -427,19 +473,7 @@ def search(plane: np.ndarray, zs: np.ndarray, n_harm: int, r_lo: int, h_max: int
     nz, nb = plane.shape
     j0 = int(np.argmin(np.abs(zs)))
     sums = harmonic_sums(plane, j0, n_harm)
-    best_lq = np.full((nz, nb), np.inf)
-    best_h = np.zeros((nz, nb), dtype=np.int64)
-    R = np.arange(nb)
-    for H, S in sums.items():
-        tau = threshold(H, sigma)
-        ok = (S >= tau) & (R[None, :] >= H * r_lo) & (R[None, :] < nb - h_max)
-        if not np.any(ok):
-            continue
-        lq = np.full((nz, nb), np.inf)
-        lq[ok] = log_tail_gamma(S[ok], H)
-        better = lq < best_lq
-        best_lq = np.where(better, lq, best_lq)
-        best_h = np.where(better, H, best_h)
+    best_h, best_lq = best_stage(sums, np.arange(nb)[None, :], nb, r_lo, h_max, sigma)
     out = []
     jj, rr = np.nonzero(best_h)
     for j, R_ in zip(jj, rr):

@@ -503,7 +503,6 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
   a.n_harm = pl->p.n_harmonics;
   a.r_lo = pl->p.r_lo;
   a.hmax = pl->hmax;
-  a.cus = pl->cu_count;
   if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "harmonic sum");
   return FDAS_OK;
@@ -534,7 +533,6 @@ static fdas_status enqueue_search(fdas_plan_t pl, const float* series, void* spe
   a.n_harm = pl->p.n_harmonics;
   a.r_lo = pl->p.r_lo;
   a.hmax = pl->hmax;
-  a.cus = pl->cu_count;
   if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "harmonic sum");
   return FDAS_OK;

@@ -81,7 +81,6 @@ struct HarmArgs {
   double z_min, z_step;
   int32_t n_series, Z, j0, n_harm, r_lo, hmax;
   int32_t max_bins;  // longest series in the batch (sets the tile grid)
-  int32_t cus;       // compute units (sizes the persistent grid)
 };
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
 

@@ -309,6 +309,67 @@ def test_harmonic_sum_ragged_batch_matches_oracle(lib, plane_dt, nh):
     assert n_cells == len(c) or abs(n_cells - len(c)) <= 0.001 * n_cells
 
 
+def test_harmonic_sum_ska_full_size_sampled(lib):
+    """The timed configuration (one 2^23-sample series, 193 trials, L = 1024,
+    bf16 storage and plane, harmonic sums to 16): every candidate record has
+    the stage and power the oracle computes from the GPU's plane at its cell,
+    and on 300 000 sampled cells plus every cell near the 8 injections the
+    passing cells are exactly the records (up to sums within 1e-5 of a
+    threshold)."""
+    import torch
+    x, inj, _ = synth.ska_single(seed=2, n=1 << 23)
+    n = len(x)
+    nb = n // 2
+    say("fdas_harmonic_sum full size, bench configuration")
+    pl = lib.Plan(store="bf16", plane="bf16", n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, n_harmonics=16,
+                  segment_len=1024)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
+    cap = 1 << 22
+    cands, count = pl.harmonic_sum(P, [n], capacity=cap)
+    pl.check(count, cap)
+    c = lib.candidates_to_numpy(cands, int(count.item()))
+    plane = P.float().cpu().numpy().reshape(pl.Z, nb)
+    j0 = 96
+    tau = {H: o.threshold(H) for H in o.stages(16)}
+
+    def oracle_at(rows, cols):
+        S = o.harmonic_sum_cells(plane, j0, 16, rows, cols)
+        h, _ = o.best_stage(S, cols, nb, r_lo=pl.hmax, h_max=pl.hmax)
+        near = np.zeros(len(rows), bool)
+        for H in S:
+            near |= np.abs(S[H] - tau[H]) <= 1e-5 * tau[H]
+        return S, h, near
+
+    assert len(c) >= 100
+    S, h, near = oracle_at(c["j"].astype(np.int64), c["R"].astype(np.int64))
+    ok = (h == c["harm"]) | near
+    assert ok.all(), np.nonzero(~ok)[0][:5]
+    same = h == c["harm"]
+    got_p = c["power"].astype(np.float64)[same]
+    want_p = np.choose(np.searchsorted([1, 2, 4, 8, 16], h[same]), [S[H][same] for H in (1, 2, 4, 8, 16)])
+    np.testing.assert_allclose(got_p, want_p, rtol=1e-5)
+    # sampled cells: random ones and the neighbourhoods of the injections
+    rng = np.random.default_rng(5)
+    rows = [rng.integers(0, pl.Z, 300_000)]
+    cols = [rng.integers(0, nb, 300_000)]
+    for i in inj:
+        for H in (1, 2, 4, 8, 16):  # where each stage's cell sees the injection as harmonic H
+            rc, mc = int(round(i.r_mean * H)), int(round(i.z * H))
+            if rc >= nb or abs(mc) > 96:
+                continue
+            jj, rr = np.meshgrid(np.arange(-4, 5) + j0 + mc, np.arange(-3, 4) + rc, indexing="ij")
+            keep = (jj >= 0) & (jj < pl.Z) & (rr >= 0) & (rr < nb)
+            rows.append(jj[keep])
+            cols.append(rr[keep])
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    _, h, near = oracle_at(rows, cols)
+    recorded = set(zip(c["j"].tolist(), c["R"].tolist()))
+    got = np.array([(int(j), int(r)) in recorded for j, r in zip(rows, cols)])
+    bad = (got != (h > 0)) & ~near
+    assert not bad.any(), (rows[bad][:5], cols[bad][:5])
+    assert (h > 0).sum() >= 50
+
+
 def test_candidate_overflow_is_reported(lib):
     n = 1 << 17
     x = synth.make_series(n, [synth.Injection(0.1, 3000.0, 8.0, 0.1)], 8, 0)

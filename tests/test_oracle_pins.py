@@ -307,9 +307,25 @@ def test_harmonic_sum_worked_fixture():
     g = json.load(open(os.path.join(GOLDEN, "harmonic_sum_worked.json")))
     P = _plane_from_formula(5, 12)
     sums = o.harmonic_sums(P, g["j0"], g["n_harm"])
-    for cell in g["cells"]:
+    rows = np.array([c["j"] for c in g["cells"]])
+    cols = np.array([c["R"] for c in g["cells"]])
+    at = o.harmonic_sum_cells(P, g["j0"], g["n_harm"], rows, cols)
+    for i, cell in enumerate(g["cells"]):
         for H, v in cell["S"].items():
             assert sums[int(H)][cell["j"], cell["R"]] == v, (cell, H)
+            assert at[int(H)][i] == v, (cell, H)
+
+
+def test_harmonic_sum_cells_agree_with_whole_plane_sums():
+    rng = np.random.default_rng(8)
+    P = rng.exponential(size=(41, 700))
+    for j0, nh in ((20, 16), (20, 8), (3, 4), (20, 1)):
+        sums = o.harmonic_sums(P, j0, nh)
+        rows = rng.integers(0, 41, 500)
+        cols = rng.integers(0, 700, 500)
+        at = o.harmonic_sum_cells(P, j0, nh, rows, cols)
+        for H in at:
+            np.testing.assert_array_equal(at[H], sums[H][rows, cols])
 
 
 def test_harmonic_sum_invariants():
@@ -343,6 +359,9 @@ def test_harmonic_sum_collects_a_pulsar_harmonic_comb():
         for H in (1, 2, 4, 8, 16):
             want = sum(1.0 + 0.01 * h for h in range(1, H + 1))
             assert abs(sums[H][j0 + H * mf, H * rf] - want) < 1e-12
+            at = o.harmonic_sum_cells(P, j0, 16, np.array([j0 + 16 * mf]), np.array([16 * rf]))
+            want16 = sum(1.0 + 0.01 * h for h in range(1, 17))
+            assert abs(at[16][0] - want16) < 1e-12
 
 
 # ------------------------------------------------------------ thresholds
@@ -361,6 +380,18 @@ def test_thresholds_closed_forms():
 def test_gaussian_sigma_large_power_no_underflow():
     s = o.gaussian_sigma(np.array([2000.0, 5000.0]), 16)
     assert np.all(np.isfinite(s)) and s[1] > s[0] > 50
+
+
+def test_best_stage_hand_worked():
+    """ln P(Gamma(1) > 25) = -25 and ln P(Gamma(2) > 30) = -30 + ln 31 = -26.57:
+    stage 2 is the more significant; stage 4 (S = 20 < 29.17) fails.  With
+    R below 2 r_lo, stage 2 is not searched and stage 1 is reported; at the
+    upper edge (R >= n_bins - h_max) nothing is."""
+    sums = {1: np.array([25.0, 25.0, 25.0]), 2: np.array([30.0, 30.0, 30.0]), 4: np.array([20.0, 20.0, 20.0])}
+    R = np.array([500, 150, 990])
+    h, lq = o.best_stage(sums, R, n_bins=1000, r_lo=100, h_max=16)
+    assert h.tolist() == [2, 1, 0]
+    assert abs(lq[0] - (-30.0 + math.log(31.0))) < 1e-12 and abs(lq[1] + 25.0) < 1e-12
 
 
 def test_search_finds_injection_and_reports_fundamental():
