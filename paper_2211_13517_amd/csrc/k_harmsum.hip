@@ -221,6 +221,9 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
     const int base = a.j0 + (kBand / H) * k * u;
     const int cs = k * (R0 / H);
+    // wave-uniform 64-bit base (row base_k, bin cs) plus a 32-bit byte offset
+    // per lane, the form the load's scalar-base addressing takes
+    const char* src = reinterpret_cast<const char*>(plane + ((int64_t)base * nb + cs));
 #pragma unroll
     for (int f0 = 0; f0 < ITEMS; f0 += CW) {
       if (f0 + wave0 >= ITEMS) continue;  // wave-uniform
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
       const int r = f / NCH, c = f - r * NCH;
       const int row = base + r, e0 = cs + c * CH;
       if (f < ITEMS && row >= 0 && row < a.Z && e0 < nb)
-        load_lds16(plane + (size_t)row * nb + e0,
+        load_lds16(src + (uint32_t)((r * nb + c * CH) * (int)sizeof(RT)),
                    reinterpret_cast<char*>(strip) + HT::off(k) * (int)sizeof(RT) + (f0 + wave0) * 16);
     }
   });
@@ -243,9 +246,10 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   };
   auto direct_ptr = [&](int k, int rel) {
     const int cs = k * (R0 / H);
-    const int row = min(max(a.j0 + (kBand / H) * k * u + rel, 0), a.Z - 1);
+    const int row = min(max(a.j0 + (kBand / H) * k * u + rel, 0), a.Z - 1);  // uniform
     const int pos = min((2 * k * tid + H) / (2 * H), nb - 1 - cs);
-    return plane + (size_t)row * nb + cs + pos;
+    return reinterpret_cast<const RT*>(reinterpret_cast<const char*>(plane + ((int64_t)row * nb + cs)) +
+                                       (uint32_t)(pos * (int)sizeof(RT)));
   };
   uint32_t dv[ND > 0 ? ND : 1][kBand];
   auto dload = [&](auto negc) {
