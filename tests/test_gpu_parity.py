@@ -309,6 +309,45 @@ def test_harmonic_sum_ragged_batch_matches_oracle(lib, plane_dt, nh):
     assert n_cells == len(c) or abs(n_cells - len(c)) <= 0.001 * n_cells
 
 
+@pytest.mark.parametrize("z_max", [0, 1, 7, 15, 16, 17])
+def test_harmonic_sum_small_z_grids(lib, z_max):
+    """Z = 2 z_max + 1 trials = 1, 3, 15, 31, 33, 35: a single trial, bands
+    cut by both plane edges, and grids one trial either side of a multiple of
+    the 16-trial band.  A noise series with a strong injection; the GPU's
+    candidates against the oracle's search of the GPU's own plane."""
+    import torch
+    n = 1 << 17
+    inj = [synth.Injection(0.06, 12000.0, min(z_max, 5.0), 0.3)]
+    x = synth.make_series(n, inj, 70 + z_max, 0)
+    say("fdas_harmonic_sum small z grid", z_max)
+    pl = lib.Plan(store="bf16", plane="bf16", n_samples=n, z_min=-float(z_max), z_max=float(z_max), z_step=1.0,
+                  n_harmonics=16, segment_len=1024)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
+    cap = 1 << 20
+    cands, count = pl.harmonic_sum(P, [n], capacity=cap)
+    pl.check(count, cap)
+    c = lib.candidates_to_numpy(cands, int(count.item()))
+    plane = plane_np(P, pl.Z, n // 2)
+    zs = o.z_grid(-z_max, z_max, 1)
+    sums = o.harmonic_sums(plane, z_max, 16)
+    tau = {H: o.threshold(H) for H in o.stages(16)}
+    want = {(k.R, k.j): k for k in o.search(plane, zs, 16, r_lo=pl.hmax, h_max=pl.hmax)}
+    got = {(int(k["R"]), int(k["j"])): k for k in c}
+    assert len(got) == len(c)
+
+    def borderline(R, j):
+        return any(abs(sums[H][j, R] - tau[H]) <= 1e-5 * tau[H] for H in tau)
+
+    for cell in set(got) ^ set(want):
+        assert borderline(*cell), cell
+    for cell in set(got) & set(want):
+        g, w = got[cell], want[cell]
+        assert int(g["harm"]) == w.harm or borderline(*cell), cell
+        if int(g["harm"]) == w.harm:
+            assert abs(float(g["power"]) - w.power) <= 1e-5 * w.power, cell
+    assert len(want) >= 5
+
+
 def test_harmonic_sum_ska_full_size_sampled(lib):
     """The timed configuration (one 2^23-sample series, 193 trials, L = 1024,
     bf16 storage and plane, harmonic sums to 16): every candidate record has
