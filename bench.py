@@ -247,36 +247,15 @@ def refine_leg(torch, fdas, synth):
             "within_1bin_1z_of_truth": float(np.mean((np.abs(rr - tr) < 1.0) & (np.abs(zz - tz) < 1.5)))}
 
 
-def local_maxima(R, j, sig, Z, radius=2):
-    """Indices of candidates that are the most significant within +-radius
-    bins and +-radius trials among one series' candidates (ties: lower key)."""
-    key = R.astype(np.int64) * Z + j
-    order = np.argsort(key, kind="stable")
-    ks, ss = key[order], sig[order]
-    keep = np.ones(len(ks), bool)
-    js = j[order]
-    for dr in range(-radius, radius + 1):
-        for dj in range(-radius, radius + 1):
-            if dr == 0 and dj == 0:
-                continue
-            ok = (js + dj >= 0) & (js + dj < Z)
-            nk = ks + dr * Z + dj
-            pos = np.minimum(np.searchsorted(ks, nk), len(ks) - 1)
-            hit = ok & (ks[pos] == nk)
-            beats = (ss[pos] > ss) | ((ss[pos] == ss) & (nk < ks))
-            keep &= ~(hit & beats)
-    return order[keep]
-
-
 def full_leg(args, torch, fdas, synth):
     """The full SKA-like run: 5925 DM trials (3050 x 2^23, 1500 x 2^22,
     1375 x 2^21), 1 % carrying one injection; BF16 storage, harmonic sums to
     16, 6 sigma, in chunks of up to 16 + 8 + 8 series whose inputs are
     generated on the device before each chunk (untimed).  The search of each
     chunk is timed with HIP events.  Candidates are reduced to local maxima
-    (+-2 bins, +-2 trials, host-side evaluation) and every maximum is refined
-    on its series' spectrum from its cell (R, z_j); the top 1024 by
-    significance are reported."""
+    (fdas_cluster, +-2 bins, +-2 trials) and every maximum is refined on its
+    series' spectrum from its cell (R, z_j); the top 1024 by significance are
+    reported."""
     N = 1 << 23
     lens_all, truths = synth.ska_full(seed=5, n=N)
     groups = [[i for i, L_ in enumerate(lens_all) if L_ == N // d] for d in (1, 2, 4)]
@@ -299,7 +278,7 @@ def full_leg(args, torch, fdas, synth):
     cands = torch.empty((cap, 8), dtype=torch.int32, device="cuda")
     count = torch.zeros(1, dtype=torch.int64, device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    search_ms, refine_ms, n_cands = 0.0, 0.0, 0
+    search_ms, cluster_ms, refine_ms, n_cands = 0.0, 0.0, 0.0, 0
     found = {}       # trial -> list of (R, z_j) of local maxima
     refined = []     # (sigma, trial, R, zj, r_ref, z_ref, P_cell, P_ref)
     for ci, c in enumerate(chunks):
@@ -320,10 +299,15 @@ def full_leg(args, torch, fdas, synth):
         n_cands += n
         if n == 0:
             continue
+        e0.record()
+        keep = pl.cluster(cands, count, 2, 2)
+        e1.record()
+        torch.cuda.synchronize()
+        cluster_ms += e0.elapsed_time(e1)
         rec = fdas.candidates_to_numpy(cands, n)
+        rec = rec[keep[:n].cpu().numpy().astype(bool)]
         for s_ in np.unique(rec["series"]):
-            sel = rec[rec["series"] == s_]
-            m = sel[local_maxima(sel["R"], sel["j"], sel["sigma"], Z)]
+            m = rec[rec["series"] == s_]
             i = c[int(s_)]
             zj = -96.0 + m["j"].astype(np.float64)
             found[i] = list(zip(m["R"].tolist(), zj.tolist()))
@@ -358,7 +342,8 @@ def full_leg(args, torch, fdas, synth):
                         f"{len(chunks)} chunks of <= 16+8+8 series, 193 templates, harmonic sums to 16, 6 sigma, "
                         "local maxima (+-2 bins, +-2 trials) refined, top 1024 reported",
             "bt_per_s": bt / (search_ms / 1e3), "search_seconds": search_ms / 1e3, "bins_x_templates": bt,
-            "candidates": n_cands, "local_maxima": len(refined), "refine_seconds": refine_ms / 1e3,
+            "candidates": n_cands, "local_maxima": len(refined), "cluster_seconds": cluster_ms / 1e3,
+            "refine_seconds": refine_ms / 1e3,
             "detectable_injections": det, "injections": sum(len(t) for t in truths),
             "recall_detectable": (hit / det) if det else None,
             "recall_top1024_refined": (hit_ref / det) if det else None,

@@ -233,6 +233,21 @@ fdas_status fdas_copy_templates(fdas_plan_t plan, void *taps_out, void *spectra_
  * array tau_host (log2(n_harmonics)+1 values). */
 fdas_status fdas_copy_thresholds(fdas_plan_t plan, double *tau_host);
 
+/* Candidate clustering (local maxima), the first step of sifting the records
+ * of fdas_harmonic_sum / fdas_search: a strong signal leaves a patch of
+ * passing cells around its peak.  Record i (i < min(*d_count, capacity)) gets
+ * keep[i] = 1 when no record of the same series with |R' - R| <= radius_r and
+ * |j' - j| <= radius_j has a larger sigma (equal sigma: the record with the
+ * smaller (j, R) wins), else 0.  cands: the records (device, with sigma filled
+ * as those calls leave them); d_count: device int64 record count; keep:
+ * device uint8 [capacity]; scratch: caller-owned device memory of at least
+ * fdas_cluster_scratch_bytes(capacity) bytes, 8-byte aligned, overwritten.
+ * Radii in [0, 64].  Enqueued on the plan's stream; allocates nothing.
+ * fdas_cluster_scratch_bytes returns -1 for a negative capacity. */
+int64_t fdas_cluster_scratch_bytes(int64_t capacity);
+fdas_status fdas_cluster(fdas_plan_t plan, const fdas_candidate *cands, const int64_t *d_count, int64_t capacity,
+                         int32_t radius_r, int32_t radius_j, void *scratch, int64_t scratch_bytes, uint8_t *keep);
+
 /* Self-test hook of the FFT engine: `batch` independent complex FFTs of
  * length L (256 ... 8192) from `in` to `out` (device, complex64, contiguous),
  * direction -1: X_k = sum_n x_n exp(-2 pi i k n / L), +1: the unnormalised

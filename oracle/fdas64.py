@@ -484,6 +484,35 @@ def search(plane: np.ndarray, zs: np.ndarray, n_harm: int, r_lo: int, h_max: int
     return out
 
 
+def local_maxima(series: np.ndarray, R: np.ndarray, j: np.ndarray, sigma: np.ndarray,
+                 radius_r: int = 2, radius_j: int = 2) -> np.ndarray:
+    """Keep flags of candidate clustering (READING: the paper's pipeline ends
+    at candidates; a standard sift keeps local maxima): record i survives when
+    no record of its series with |R' - R| <= radius_r and |j' - j| <= radius_j
+    has a larger sigma, equal sigmas going to the smaller (j, R).  Sorted
+    lookups over the 8- or 24-cell neighbourhood."""
+    series = np.asarray(series, np.int64)
+    key = (series << 34) | (np.asarray(j, np.int64) << 22) | np.asarray(R, np.int64)
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    ss = np.asarray(sigma)[order]
+    keep = np.ones(len(ks), bool)
+    Rs, js, sers = np.asarray(R, np.int64)[order], np.asarray(j, np.int64)[order], series[order]
+    for dj in range(-radius_j, radius_j + 1):
+        for dr in range(-radius_r, radius_r + 1):
+            if dj == 0 and dr == 0:
+                continue
+            ok = (js + dj >= 0) & (Rs + dr >= 0) & (js + dj < (1 << 12)) & (Rs + dr < (1 << 22))
+            nk = (sers << 34) | ((js + dj) << 22) | (Rs + dr)
+            pos = np.minimum(np.searchsorted(ks, nk), len(ks) - 1)
+            hit = ok & (ks[pos] == nk)
+            beats = (ss[pos] > ss) | ((ss[pos] == ss) & (nk < ks))
+            keep &= ~(hit & beats)
+    out = np.zeros(len(ks), bool)
+    out[order] = keep
+    return out
+
+
 # ---------------------------------------------------------------- refinement
 
 

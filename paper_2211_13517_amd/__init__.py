@@ -51,7 +51,7 @@ EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace
            "fdas_spectrum", "fdas_convolve_spectrum", "fdas_convolve", "fdas_harmonic_sum", "fdas_check",
            "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
-           "fdas_last_error"]
+           "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster"]
 
 _lib = None
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
         "fdas_autotune": ([POINTER(Params), c_int, P, P, c_int64, POINTER(Params), POINTER(c_double)], c_int),
         "fdas_copy_templates": ([P, P, P], c_int),
         "fdas_copy_thresholds": ([P, POINTER(c_double)], c_int),
+        "fdas_cluster_scratch_bytes": ([c_int64], c_int64),
+        "fdas_cluster": ([P, P, P, c_int64, c_int32, c_int32, P, c_int64, P], c_int),
         "fdas_test_fft": ([P, c_int32, c_int32, P, P, c_int64], c_int),
         "fdas_plan_destroy": ([P], c_int),
         "fdas_last_error": ([P], c_char_p),
@@ -249,6 +251,20 @@ class Plan:
                                          len(lengths), None if spectrum is None else c_void_p(spectrum.data_ptr()),
                                          c_void_p(plane.data_ptr()), nbytes, c_void_p(cands.data_ptr()),
                                          cands.shape[0], c_void_p(count.data_ptr()), 1 if use_graph else 0))
+
+    def cluster(self, cands, count, radius_r: int = 2, radius_j: int = 2):
+        """Local maxima among candidate records (see fdas_cluster): returns a
+        uint8 device tensor [capacity], 1 for records to keep."""
+        import torch
+        cap = int(cands.shape[0])
+        nbytes = int(self.lib.fdas_cluster_scratch_bytes(cap))
+        if getattr(self, "_cluster_scratch", None) is None or self._cluster_scratch.numel() < nbytes:
+            self._cluster_scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        keep = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.fdas_cluster(self.handle, c_void_p(cands.data_ptr()), c_void_p(count.data_ptr()), cap,
+                                          radius_r, radius_j, c_void_p(self._cluster_scratch.data_ptr()), nbytes,
+                                          c_void_p(keep.data_ptr())))
+        return keep
 
     def check(self, count=None, capacity: int = 0):
         """Synchronises and raises FdasError for latched device conditions."""

@@ -93,6 +93,11 @@ hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r
 hipError_t launch_refine(int sdt, const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters, int margin,
                          double* p_final, hipStream_t st);
 
+// candidate clustering
+int64_t cluster_scratch_bytes(int64_t capacity);
+hipError_t launch_cluster(const fdas_candidate* c, const unsigned long long* count, int64_t capacity, int rr, int rj,
+                          void* scratch, uint8_t* keep, int cus, hipStream_t st);
+
 // small helpers (fill kernels are graph-capture safe, unlike memset nodes)
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t value, hipStream_t st);
 hipError_t launch_fill_noise(void* spec, int sdt, int64_t nbins, uint64_t seed, hipStream_t st);

@@ -94,3 +94,11 @@ def test_binding_refuses_missing_library(tmp_path):
             fdas.load(str(tmp_path / "nope.so"))
     finally:
         fdas._lib = saved
+
+
+def test_cluster_scratch_size_is_host_only(lib):
+    L = lib
+    assert L.fdas_cluster_scratch_bytes(-1) == -1
+    # a power-of-two table of at least twice the records, 12 bytes a slot
+    assert L.fdas_cluster_scratch_bytes(1000) == 2048 * 12
+    assert L.fdas_cluster_scratch_bytes(1 << 20) == (1 << 21) * 12

@@ -309,6 +309,36 @@ def test_harmonic_sum_ragged_batch_matches_oracle(lib, plane_dt, nh):
     assert n_cells == len(c) or abs(n_cells - len(c)) <= 0.001 * n_cells
 
 
+def test_cluster_matches_oracle_local_maxima(lib):
+    """fdas_cluster on the records of a ragged batch search equals the
+    oracle's local maxima of the same records, for three neighbourhoods, and
+    when the record count exceeds the buffer."""
+    import torch
+    n = 1 << 18
+    lens = [n, n // 2, n, n // 2]
+    xs, truths = synth.batch_series(lens, seed=62, inj_per_series=(1, 2), amp=(0.04, 0.07), z_abs=44.0)
+    x, offs, _ = synth.concat(xs)
+    say("fdas_cluster")
+    pl = lib.Plan(store="bf16", plane="bf16", n_samples=n, max_batch_samples=sum(lens), z_min=-48.0, z_max=48.0,
+                  z_step=1.0, n_harmonics=16, segment_len=1024)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), offs, lens)
+    cap = 1 << 22
+    cands, count = pl.harmonic_sum(P, lens, capacity=cap)
+    pl.check(count, cap)
+    n_rec = int(count.item())
+    c = lib.candidates_to_numpy(cands, n_rec)
+    for rr, rj in ((2, 2), (0, 3), (5, 1)):
+        keep = pl.cluster(cands, count, rr, rj)[:n_rec].cpu().numpy().astype(bool)
+        want = o.local_maxima(c["series"], c["R"], c["j"], c["sigma"], rr, rj)
+        assert np.array_equal(keep, want), (rr, rj, np.nonzero(keep != want)[0][:5])
+        assert 0 < keep.sum() < n_rec
+    # more records than the buffer holds: the first 500 are clustered
+    small = cands[:500].clone()
+    keep = pl.cluster(small, count, 2, 2).cpu().numpy().astype(bool)
+    c5 = c[:500]
+    assert np.array_equal(keep, o.local_maxima(c5["series"], c5["R"], c5["j"], c5["sigma"], 2, 2))
+
+
 @pytest.mark.parametrize("z_max", [0, 1, 7, 15, 16, 17])
 def test_harmonic_sum_small_z_grids(lib, z_max):
     """Z = 2 z_max + 1 trials = 1, 3, 15, 31, 33, 35: a single trial, bands

@@ -394,6 +394,33 @@ def test_best_stage_hand_worked():
     assert abs(lq[0] - (-30.0 + math.log(31.0))) < 1e-12 and abs(lq[1] + 25.0) < 1e-12
 
 
+def test_local_maxima_against_brute_force():
+    rng = np.random.default_rng(11)
+    for trial in range(15):
+        n = 150
+        cells = set()
+        while len(cells) < n:
+            cells.add((int(rng.integers(0, 3)), int(rng.integers(0, 30)), int(rng.integers(0, 9))))
+        ser, R, j = (np.array(v) for v in zip(*cells))
+        sig = rng.integers(0, 6, n).astype(np.float32)   # many ties
+        got = o.local_maxima(ser, R, j, sig)
+        key = ser * 2 ** 34 + j * 2 ** 22 + R
+        for a in range(n):
+            beaten = any(ser[b] == ser[a] and abs(R[b] - R[a]) <= 2 and abs(j[b] - j[a]) <= 2 and
+                         (sig[b] > sig[a] or (sig[b] == sig[a] and key[b] < key[a])) for b in range(n) if b != a)
+            assert got[a] == (not beaten), (trial, a)
+
+
+def test_local_maxima_hand_worked():
+    # a 3x3 patch around (R, j) = (100, 10) peaking at its centre, a lone record
+    # 3 bins away (outside the radius) and a record of another series
+    R = np.array([99, 100, 101, 99, 100, 101, 99, 100, 101, 103, 100])
+    j = np.array([9, 9, 9, 10, 10, 10, 11, 11, 11, 10, 10])
+    s = np.array([0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1])
+    sig = np.array([6.1, 6.5, 6.2, 7.0, 9.0, 7.5, 6.0, 6.4, 6.3, 8.0, 6.0], np.float32)
+    assert o.local_maxima(s, R, j, sig).tolist() == [False] * 4 + [True] + [False] * 4 + [True, True]
+
+
 def test_search_finds_injection_and_reports_fundamental():
     n = 1 << 17
     x = synth.make_series(n, [synth.Injection(0.05, 5000.0, 12.0, 0.5)], 3, 0)
