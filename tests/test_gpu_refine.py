@@ -40,6 +40,9 @@ def test_rz_power_and_y_match_oracle(lib):
     st = starts.copy()
     st[:4, 1] = [0.0, 1e-3, -0.02, 0.3]   # small-|z| branch and z = 0
     st[4:8, 0] = np.floor(st[4:8, 0])     # integer r
+    nb = n // 2                           # windows cut by the spectrum's ends
+    st[8:14, 0] = [0.3, 5.5, 17.9, nb - 3.2, nb - 0.5, nb - 20.25]
+    st[8:14, 1] = [0.0, 30.0, -60.0, 12.0, -0.01, 90.0]
     r = torch.tensor(st[:, 0], dtype=torch.float64, device="cuda")
     z = torch.tensor(st[:, 1], dtype=torch.float64, device="cuda")
     p, y = pl.rz_power(spec, r, z)
