@@ -101,10 +101,10 @@ constexpr int kConvWaves = 4;  // wavefronts per block of the one-wavefront-per-
 template <int L>
 using ConvShape = FftShape<L, 16, 16>;
 
-// 16-bit storage leaves room for three wavefronts per SIMD; FP32 storage (twice
-// the template registers) runs two.
+// Two wavefronts per SIMD: with the template prefetch in registers a third
+// wavefront (possible for 16-bit storage) measured no faster.
 template <int L, int SDT, int PDT>
-__global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(SDT == FDAS_F32 ? 2 : 3)))
+__global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(2)))
 void k_conv_wave(ConvArgs a) {
   using FS = ConvShape<L>;
   static_assert(FS::NT == 64, "one wavefront per FFT");
