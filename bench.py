@@ -218,7 +218,7 @@ def cpu_baseline(o, x, rows=24):
 
 
 def refine_leg(torch, fdas, synth):
-    """Row a12 at its own workload: one 2^22-sample series, 4096 candidates
+    """Refinement at its own workload: one 2^22-sample series, 4096 candidates
     perturbed by up to 0.5 bin and 1 z from injected truths, 40 ascent
     iterations each (FP64 positions, FP32 spectrum)."""
     n = 1 << 22
@@ -351,7 +351,7 @@ def full_leg(args, torch, fdas, synth):
 
 
 def batch_leg(args, torch, fdas, synth):
-    """Row a11: 512 uneven DM trials, chunks of 16 x 2^23 + 8 x 2^22 + 8 x 2^21
+    """Batching: 512 uneven DM trials, chunks of 16 x 2^23 + 8 x 2^22 + 8 x 2^21
     series (one HIP graph, replayed per chunk after the chunk's series are
     copied into the working buffer); BF16 storage, harmonic sums to 16, 6 sigma."""
     N = 1 << 23
@@ -428,8 +428,8 @@ def main():
     global _torch
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md but not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over "
+                                   "GPUs is designed but not built)"}))
         sys.exit(2)
     import torch
     _torch = torch

@@ -126,7 +126,7 @@ fdas_status fdas_set_workspace(fdas_plan_t plan, void *dev_ptr, int64_t bytes);
  * Needs a workspace.  Must run before fdas_convolve*. */
 fdas_status fdas_make_templates(fdas_plan_t plan);
 
-/* Rows a1-a2: real FFT of every series, A_r = sum_n x_n exp(-2 pi i r n/N) for
+/* Spectrum: real FFT of every series, A_r = sum_n x_n exp(-2 pi i r n/N) for
  * r < N/2 (Nyquist dropped, A_0 set to 0), then normalisation: NONE; VARIANCE
  * A/sqrt(N sigma^2); MEDIAN A sqrt(ln2/m_b) with m_b the lower median of |A|^2
  * (rank (B-1)/2) in each block of B bins (a zero median scales the block by 0).
@@ -134,7 +134,7 @@ fdas_status fdas_make_templates(fdas_plan_t plan);
 fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out);
 
-/* Rows a4-a8 from a normalised spectrum (store_dtype, packed): overlap-save
+/* Convolution from a normalised spectrum (store_dtype, packed): overlap-save
  * segments of L bins starting at s U - h_max (zero outside [0, N/2)), one
  * forward FFT per segment, then for every template j: product with T_j,
  * inverse FFT, and P[j][s U + i] = |y[h_max + i]|^2 for i < U, i.e.
@@ -144,13 +144,13 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
 fdas_status fdas_convolve_spectrum(fdas_plan_t plan, const void *spectrum, const int64_t *lengths_host,
                                    int32_t n_series, void *plane_out, int64_t plane_bytes);
 
-/* Rows a1-a8 in one call: fdas_spectrum then fdas_convolve_spectrum.
+/* Spectrum and convolution in one call: fdas_spectrum then fdas_convolve_spectrum.
  * spectrum_out may be NULL, in which case the spectrum lives in the workspace. */
 fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out,
                           void *plane_out, int64_t plane_bytes);
 
-/* Rows a9-a10: nested harmonic sums and thresholding over a packed plane.
+/* Harmonic sums: nested harmonic sums and thresholding over a packed plane.
  * For cell (R, j) with m = j - j0 (j0 the z = 0 trial) and H the top stage,
  *   S_H(R, j) = sum_{k=1}^{H} P[j0 + sgn(m) floor((2k|m| + H)/(2H))][floor((2kR + H)/(2H))],
  * and the lower stages H' use the terms k = H/H', 2H/H', ..., H.  A cell is
@@ -164,7 +164,7 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);
 
-/* Row a12, forward: Fourier-interpolated matched-filter power at off-grid
+/* Off-grid power, forward: Fourier-interpolated matched-filter power at off-grid
  * candidates (section 2.1's matched filter evaluated between grid points):
  *   y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),
  *   w = kernel_margin + ceil(|z|/2) (32 bins at z = 0), A_k = 0 outside [0, n_bins),
@@ -176,7 +176,7 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
 fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r, const double *z,
                           int64_t n, double *p, void *y_out);
 
-/* Row a12, adjoint: given the upstream gradient grad_p[i] of a real loss with
+/* Off-grid power, adjoint: given the upstream gradient grad_p[i] of a real loss with
  * respect to p[i], writes grad_r[i] = grad_p 2 Re(conj(y) dy/dr),
  * grad_z[i] = grad_p 2 Re(conj(y) dy/dz) (dy/dr = -sum A_k conj(d rho/dq),
  * dy/dz = sum A_k conj(d rho/dz), FP64), and, if grad_spectrum is non-NULL,
@@ -188,7 +188,7 @@ fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n
                                const double *z, const void *y, const double *grad_p, int64_t n, double *grad_r,
                                double *grad_z, void *grad_spectrum);
 
-/* Row a12, refinement: n_iter steps of preconditioned gradient ascent of
+/* Refinement: n_iter steps of preconditioned gradient ascent of
  * P(r, z) per candidate (step (dP/dr / (2 a P), dP/dz / (2 b P)) with
  * a = pi^2/3, b = pi^2/180, clamped to 0.25 bin and 2 z, halved until P
  * grows), r and z updated in place (double [n]), and the final power evaluated
@@ -196,20 +196,20 @@ fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n
 fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, double *r, double *z, int64_t n,
                         int32_t n_iter, double *p_final);
 
-/* Rows a1-a10 for one batch in one call: resets *d_count (with a kernel),
+/* The whole search for one batch in one call: resets *d_count (with a kernel),
  * then spectrum, convolution and harmonic sums exactly as fdas_spectrum,
  * fdas_convolve_spectrum and fdas_harmonic_sum.  With use_graph != 0 the
  * launches are captured once into a HIP graph (the plan's stream must not be
  * the default stream) and replayed on later calls with the same pointers,
  * offsets and lengths; the batch descriptors are uploaded before capture.
- * Row a11: the batch may mix full-length and decimated series; the
+ * The batch may mix full-length and decimated series; the
  * convolution tiles of all series go to one persistent launch. */
 fdas_status fdas_search(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                         const int64_t *lengths_host, int32_t n_series, void *spectrum_out, void *plane_out,
                         int64_t plane_bytes, fdas_candidate *cands, int64_t capacity, int64_t *d_count,
                         int32_t use_graph);
 
-/* Row a11, tuning: times the convolution of one full-length noise spectrum
+/* Tuning: times the convolution of one full-length noise spectrum
  * for every segment length L in {1024, 2048, 4096, 8192} allowed by the z
  * range and templates_per_tile in {auto, 12, 24, 48, 96} on `device`/`hip_stream`,
  * using `scratch` (device memory, at least workspace + spectrum + plane of one

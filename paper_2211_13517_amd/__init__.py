@@ -245,7 +245,7 @@ class Plan:
 
     def search(self, series, offsets: Sequence[int], lengths: Sequence[int], plane, cands, count,
                spectrum=None, use_graph: bool = False):
-        """Rows a1-a10 for one batch (optionally through a captured HIP graph)."""
+        """The whole search, spectrum to candidates, for one batch (optionally through a captured HIP graph)."""
         nbytes = plane.numel() * plane.element_size()
         self._check(self.lib.fdas_search(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
                                          len(lengths), None if spectrum is None else c_void_p(spectrum.data_ptr()),

@@ -88,7 +88,7 @@ struct fdas_plan_s {
   bool batch_valid = false;
   SeriesDesc* h_desc_pinned = nullptr;
   int32_t* h_lists_pinned = nullptr;
-  // captured a1-a10 graph and the arguments it was captured for
+  // captured search graph and the arguments it was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uintptr_t> graph_key;
@@ -510,7 +510,7 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
 
 }  // extern "C"
 
-// Enqueues a1-a10 for the current batch (descriptors already uploaded).
+// Enqueues the whole search for the current batch (descriptors already uploaded).
 static fdas_status enqueue_search(fdas_plan_t pl, const float* series, void* spec, void* plane, int64_t plane_bytes,
                                   fdas_candidate* cands, int64_t capacity, int64_t* d_count) {
   hipError_t e = launch_fill_i64(d_count, 1, 0, pl->stream);

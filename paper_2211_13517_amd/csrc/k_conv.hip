@@ -1,4 +1,4 @@
-// Rows a4-a8: overlap-save correlation with every template and the power plane,
+// Overlap-save correlation with every template and the power plane,
 // fused in one kernel so that the complex products never leave the chip.
 //
 // Work unit ("tile"): one segment of one series and one group of templates.

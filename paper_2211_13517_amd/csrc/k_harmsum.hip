@@ -1,4 +1,4 @@
-// Rows a9-a10: nested incoherent harmonic sums over the power plane,
+// Nested incoherent harmonic sums over the power plane,
 // thresholds and candidate compaction.
 //
 // Cell (R, j) holds the sum for a signal whose H-th harmonic sits at bin R and

@@ -1,4 +1,4 @@
-// Row a12: Fourier-interpolated power P(r, z) at off-grid candidates, its
+// Fourier-interpolated power P(r, z) at off-grid candidates, its
 // adjoint, and gradient-ascent refinement.
 //
 // y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),

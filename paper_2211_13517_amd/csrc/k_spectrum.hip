@@ -1,4 +1,4 @@
-// Rows a1-a2: real FFT of each series and spectrum normalisation.
+// Real FFT of each series and spectrum normalisation.
 //
 // A real series x of N samples is read as M = N/2 complex values
 // z[n] = x[2n] + i x[2n+1] and transformed with a four-step FFT, M = M1 * M2:

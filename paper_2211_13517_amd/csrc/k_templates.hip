@@ -1,4 +1,4 @@
-// Row a3: the FP64 template bank.
+// The FP64 template bank.
 //
 // For acceleration trial z_j = z_min + j dz the matched filter has taps
 //   t_q = conj(rho(q, z_j)) / sqrt(E_j),  |q| <= h_j = ceil(|z_j|/2) + m,

@@ -40,7 +40,7 @@ template <> struct ShapeOf<2048> { using type = FftShape<2048, 32, 16>; };
 template <> struct ShapeOf<4096> { using type = FftShape<4096, 16, 16>; };
 template <> struct ShapeOf<8192> { using type = FftShape<8192, 16, 16>; };
 
-// a1-a2
+// spectrum
 hipError_t launch_rfft_columns(int M1, int M2, const float* x, const SeriesDesc* desc, const int32_t* list,
                                int nlist, c32* Y, const c32* tw, hipStream_t st);
 hipError_t launch_rfft_rows(int M1, int M2, const SeriesDesc* desc, const int32_t* list, int nlist,
@@ -49,14 +49,14 @@ hipError_t launch_unpack_normalise(int sdt, int M, int B, int mode, double var_s
                                    const int32_t* list, int nlist, const c32* Zb, void* spec, int32_t* status,
                                    hipStream_t st);
 
-// a3
+// templates
 hipError_t launch_exp_table(int L, c64* tab, hipStream_t st);
 hipError_t launch_template_taps(double z_min, double z_step, int Z, int margin, int hmax, c64* taps,
                                 hipStream_t st);
 hipError_t launch_template_spectra(int sdt, const c64* taps, const c64* tab, int Z, int hmax, int L, void* out,
                                    hipStream_t st);
 
-// a4-a8
+// convolution
 struct ConvArgs {
   const void* spec;        // packed normalised spectrum, store dtype
   const void* tspec;       // template spectra [Z][L], store dtype
@@ -70,7 +70,7 @@ hipError_t launch_conv(int L, int sdt, int pdt, const ConvArgs& a, int grid, hip
 int conv_waves_per_block(int L);
 int conv_blocks_per_cu(int L, int sdt, int pdt);  // resident blocks per CU (occupancy query)
 
-// a9-a10
+// harmonic sums
 struct HarmArgs {
   const void* plane;
   const SeriesDesc* desc;
@@ -84,7 +84,7 @@ struct HarmArgs {
 };
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
 
-// a12
+// off-grid power and refinement
 hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,
                            double* p, c64* y, hipStream_t st);
 hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r, const double* z, const c64* y,

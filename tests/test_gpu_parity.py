@@ -463,7 +463,7 @@ def test_nonfinite_input_is_reported(lib):
     pl.check()  # the latch clears
 
 
-# ---------------------------------------------------------------- a11: batch, graph, autotune
+# ---------------------------------------------------------------- batch, graph, autotune
 
 def test_search_graph_replays_match_eager(lib):
     """fdas_search captured into a HIP graph: every replay (with eager work and

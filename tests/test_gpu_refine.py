@@ -1,4 +1,4 @@
-"""GPU parity of row a12: off-grid P(r, z), its adjoint and refinement,
+"""GPU parity of the off-grid power P(r, z), its adjoint and refinement,
 through the C ABI, against the FP64 oracle evaluated on the same spectrum."""
 import numpy as np
 import pytest
