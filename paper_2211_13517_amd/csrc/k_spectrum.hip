@@ -17,37 +17,77 @@ namespace fdas {
 
 constexpr int kWaves = 8;  // FFTs (one per wavefront) per 512-thread block
 
+// Both passes move data between HBM and the wavefronts' thread-strided FFT
+// layout (lane l holds points l + 64 c) through 64-row x 8-column chunks in
+// LDS: the block's 8 columns (or rows) are 8 consecutive complex values in
+// memory, so every global access of a chunk is a run of 64 bytes instead of
+// one 8-byte value per lane at a 16 KB stride.  The chunks borrow the FFT
+// exchange buffers, which are idle before and after the transform.
+struct Chunk {
+  static constexpr int PITCH = 9;                // floats per row: 8 columns + pad (no bank conflicts)
+  static constexpr int FLOATS = 2 * 64 * PITCH;  // re and im planes of one chunk
+};
+
+// every thread: chunk element (row t / 8, column t % 8) <-> this lane's (l, column w)
+__device__ __forceinline__ void chunk_put(float* buf, int row, int col, c32 v) {
+  buf[row * Chunk::PITCH + col] = v.re;
+  buf[64 * Chunk::PITCH + row * Chunk::PITCH + col] = v.im;
+}
+__device__ __forceinline__ c32 chunk_get(const float* buf, int row, int col) {
+  return {buf[row * Chunk::PITCH + col], buf[64 * Chunk::PITCH + row * Chunk::PITCH + col]};
+}
+
 template <int M1>
 __global__ __launch_bounds__(512) void k_rfft_cols(const float* __restrict__ x, const SeriesDesc* __restrict__ desc,
                                                    const int32_t* __restrict__ list, int M2, c32* __restrict__ Y,
                                                    const c32* __restrict__ twg) {
   using FS = typename ShapeOf<M1>::type;
+  constexpr int P = FS::P;
+  static_assert(kWaves * FS::XBUF * 2 >= 2 * Chunk::FLOATS, "chunks fit in the exchange buffers");
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[kWaves][FS::XBUF];
   stage_table(tw, twg, FS::TW_SIZE);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int n2 = blockIdx.x * kWaves + wave;
-  if (n2 >= M2) return;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int n2_0 = blockIdx.x * kWaves;  // M2 is a multiple of kWaves
   const SeriesDesc d = desc[list[blockIdx.y]];
   const uint32_t M = (uint32_t)M1 * (uint32_t)M2;
   const float2* z = reinterpret_cast<const float2*>(x + d.in_off);
-  c32 v[FS::P];
-  static_for<0, FS::P>([&](auto cc) {
+  float* cbuf = reinterpret_cast<float*>(&xb[0][0]);
+  // every load of the column group in flight at once
+  float2 g[P];
+  static_for<0, P>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    const float2 t = z[(size_t)(lane + 64 * c) * M2 + n2];
-    v[c] = {t.x, t.y};
+    g[c] = z[(size_t)(64 * c + (t >> 3)) * M2 + n2_0 + (t & 7)];
   });
+  c32 v[P];
+  static_for<0, P>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    float* buf = cbuf + (c & 1) * Chunk::FLOATS;
+    chunk_put(buf, t >> 3, t & 7, c32{g[c].x, g[c].y});
+    __syncthreads();
+    v[c] = chunk_get(buf, lane, wave);
+  });
+  __syncthreads();  // the chunks' LDS becomes the FFT exchange buffers
   fft_run<FS, -1, false>(v, xb[wave], tw, lane);
-  c32* y = Y + d.spec_off;
+  const int n2 = n2_0 + wave;
   const float inv = 1.0f / (float)M;
-  static_for<0, FS::P>([&](auto cc) {
+  static_for<0, P>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     const uint32_t k1 = lane + 64 * c;
     const uint32_t idx = ((uint32_t)n2 * k1) & (M - 1);
     float s, co;
     sincospif(-2.0f * (float)idx * inv, &s, &co);
-    y[(size_t)k1 * M2 + n2] = cmul(v[c], c32{co, s});
+    v[c] = cmul(v[c], c32{co, s});
+  });
+  __syncthreads();  // and back to chunks
+  c32* y = Y + d.spec_off;
+  static_for<0, P>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    float* buf = cbuf + (c & 1) * Chunk::FLOATS;
+    chunk_put(buf, lane, wave, v[c]);
+    __syncthreads();
+    const c32 o = chunk_get(buf, t >> 3, t & 7);
+    y[(size_t)(64 * c + (t >> 3)) * M2 + n2_0 + (t & 7)] = o;
   });
 }
 
@@ -57,25 +97,32 @@ __global__ __launch_bounds__(512) void k_rfft_rows(const SeriesDesc* __restrict_
                                                    const c32* __restrict__ Y, c32* __restrict__ Zb,
                                                    const c32* __restrict__ twg) {
   using FS = typename ShapeOf<M2>::type;
+  constexpr int P = FS::P;
+  static_assert(kWaves * FS::XBUF * 2 >= 2 * Chunk::FLOATS, "chunks fit in the exchange buffers");
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[kWaves][FS::XBUF];
   stage_table(tw, twg, FS::TW_SIZE);
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int k1 = blockIdx.x * kWaves + wave;
-  if (k1 >= M1) return;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int k1_0 = blockIdx.x * kWaves;  // M1 is a multiple of kWaves
   const SeriesDesc d = desc[list[blockIdx.y]];
-  const c32* y = Y + d.spec_off + (size_t)k1 * M2;
-  c32 v[FS::P];
-  static_for<0, FS::P>([&](auto cc) {
+  const c32* y = Y + d.spec_off + (size_t)(k1_0 + wave) * M2;
+  c32 v[P];
+  static_for<0, P>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     v[c] = y[lane + 64 * c];
   });
   fft_run<FS, -1, false>(v, xb[wave], tw, lane);
+  __syncthreads();  // the exchange buffers become chunks
+  float* cbuf = reinterpret_cast<float*>(&xb[0][0]);
   c32* zo = Zb + d.spec_off;
-  static_for<0, FS::P>([&](auto cc) {
+  static_for<0, P>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    zo[(size_t)k1 + (size_t)M1 * (lane + 64 * c)] = v[c];
+    float* buf = cbuf + (c & 1) * Chunk::FLOATS;
+    chunk_put(buf, lane, wave, v[c]);
+    __syncthreads();
+    // Z[k1 + M1 k2]: the block's 8 rows k1 are 8 consecutive outputs
+    zo[(size_t)k1_0 + (t & 7) + (size_t)M1 * (64 * c + (t >> 3))] = chunk_get(buf, t >> 3, t & 7);
   });
 }
 
