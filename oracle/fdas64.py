@@ -323,6 +323,37 @@ def power_plane(a_norm: np.ndarray, zs: Sequence[float], margin: int = 16,
     return out
 
 
+def interbin_plane(a_norm: np.ndarray, zs: Sequence[float], margin: int = 16,
+                   rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """The power plane at half-bin resolution (interbinning; READING, the paper
+    is silent): column 2r holds P[j][r] = |y_j(r)|^2 and column 2r + 1 the
+    half-bin power |y_j(r) - y_j(r + 1)|^2 / 2, with y_j(N/2) taken from the
+    spectrum extended by zeros like every other out-of-range bin.
+
+    Why this value: the template autocorrelation sum_q rho(q + d, z) conj rho(q, z)
+    is, by Parseval over u in [0, 1), the integral of exp(-2 pi i d u), i.e.
+    exp(-i pi d) sinc(d) for every z.  So after the matched filter a signal at
+    rbar leaves y(r) proportional to exp(-i pi (r - rbar)) sinc(r - rbar), and
+    for rbar midway between r and r + 1 the two neighbours are (2/pi) of its
+    amplitude with opposite signs: (pi/4)(y_r - y_{r+1}) recovers it.  The same
+    autocorrelation vanishes at integer lags (sinc(1) = 0), so noise outputs of
+    neighbouring bins are uncorrelated and E|y_r - y_{r+1}|^2 = 2; the factor
+    8/pi^2 that brings noise back to unit mean turns (pi/4)^2 into 1/2.  A tone
+    midway between bins then keeps 8/pi^2 = 0.81 of its power instead of
+    sinc(1/2)^2 = 0.405."""
+    taps, _ = template_taps(zs, margin)
+    rows = range(len(zs)) if rows is None else rows
+    a_ext = np.concatenate([np.asarray(a_norm, dtype=np.complex128), [0.0]])
+    nb = len(a_norm)
+    out = np.empty((len(rows), 2 * nb), dtype=np.float64)
+    for i, j in enumerate(rows):
+        y = correlate(a_ext, taps[j])        # bins 0 .. N/2
+        d = y[:-1] - y[1:]
+        out[i, 0::2] = y[:-1].real ** 2 + y[:-1].imag ** 2
+        out[i, 1::2] = 0.5 * (d.real ** 2 + d.imag ** 2)
+    return out
+
+
 def power_cells(a_norm: np.ndarray, taps: np.ndarray, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
     """P at individual cells (row j, bin r) by the direct sum, for sampled checks."""
     rows = np.asarray(rows)
@@ -463,23 +494,25 @@ def best_stage(sums: Dict[int, np.ndarray], R: np.ndarray, n_bins: int, r_lo: in
 
 
 def search(plane: np.ndarray, zs: np.ndarray, n_harm: int, r_lo: int, h_max: int,
-           sigma: float = 6.0, series: int = 0) -> List[Candidate]:
+           sigma: float = 6.0, series: int = 0, res: int = 1) -> List[Candidate]:
     """Threshold the harmonic sums and emit at most one candidate per cell.
 
     Cell (R, j) is searched at stage H when R >= H r_lo and R < B_r - h_max;
     it passes when S_H >= tau_H.  Among passing stages the one with the smallest
     noise tail probability (largest Gaussian significance) is reported, with
-    fundamental r = R/H and z = z_j/H."""
+    fundamental r = R/H and z = z_j/H.  With res = 2 the plane is the
+    half-bin one (interbin_plane): R counts half bins, the limits are
+    2 H r_lo and 2 (B_r - h_max), and r = R / (2 H) bins."""
     nz, nb = plane.shape
     j0 = int(np.argmin(np.abs(zs)))
     sums = harmonic_sums(plane, j0, n_harm)
-    best_h, best_lq = best_stage(sums, np.arange(nb)[None, :], nb, r_lo, h_max, sigma)
+    best_h, best_lq = best_stage(sums, np.arange(nb)[None, :], nb, res * r_lo, res * h_max, sigma)
     out = []
     jj, rr = np.nonzero(best_h)
     for j, R_ in zip(jj, rr):
         H = int(best_h[j, R_])
         S = float(sums[H][j, R_])
-        out.append(Candidate(series, H, int(R_), int(j), R_ / H, float(zs[j]) / H, S,
+        out.append(Candidate(series, H, int(R_), int(j), R_ / (res * H), float(zs[j]) / H, S,
                              float(-sps.ndtri_exp(best_lq[j, R_]))))
     return out
 
@@ -490,9 +523,10 @@ def local_maxima(series: np.ndarray, R: np.ndarray, j: np.ndarray, sigma: np.nda
     at candidates; a standard sift keeps local maxima): record i survives when
     no record of its series with |R' - R| <= radius_r and |j' - j| <= radius_j
     has a larger sigma, equal sigmas going to the smaller (j, R).  Sorted
-    lookups over the 8- or 24-cell neighbourhood."""
+    lookups over the 8- or 24-cell neighbourhood (R < 2^23 holds half-bin
+    cells too)."""
     series = np.asarray(series, np.int64)
-    key = (series << 34) | (np.asarray(j, np.int64) << 22) | np.asarray(R, np.int64)
+    key = (series << 35) | (np.asarray(j, np.int64) << 23) | np.asarray(R, np.int64)
     order = np.argsort(key, kind="stable")
     ks = key[order]
     ss = np.asarray(sigma)[order]
@@ -502,8 +536,8 @@ def local_maxima(series: np.ndarray, R: np.ndarray, j: np.ndarray, sigma: np.nda
         for dr in range(-radius_r, radius_r + 1):
             if dj == 0 and dr == 0:
                 continue
-            ok = (js + dj >= 0) & (Rs + dr >= 0) & (js + dj < (1 << 12)) & (Rs + dr < (1 << 22))
-            nk = (sers << 34) | ((js + dj) << 22) | (Rs + dr)
+            ok = (js + dj >= 0) & (Rs + dr >= 0) & (js + dj < (1 << 12)) & (Rs + dr < (1 << 23))
+            nk = (sers << 35) | ((js + dj) << 23) | (Rs + dr)
             pos = np.minimum(np.searchsorted(ks, nk), len(ks) - 1)
             hit = ok & (ks[pos] == nk)
             beats = (ss[pos] > ss) | ((ss[pos] == ss) & (nk < ks))

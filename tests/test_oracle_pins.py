@@ -295,6 +295,75 @@ def test_noise_rows_have_unit_mean_power():
     assert np.all(np.abs(frac - math.exp(-3)) < 0.005)
 
 
+# ------------------------------------------------------------ interbinning
+
+def test_interbin_midway_tone_keeps_8_over_pi2():
+    # a z = 0 tone midway between bins 5000 and 5001: each neighbour holds
+    # (2/pi)^2 of the peak, the half-bin column (8/pi^2) of it (sinc response
+    # of the DFT, up to the O(1/N) image term)
+    n, a = 1 << 17, 0.05
+    x = a * np.cos(2 * np.pi * 5000.5 * np.arange(n) / n + 0.3)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    P2 = o.interbin_plane(s, [0.0])
+    assert abs(P2[0, 2 * 5000 + 1] - 81.92 * 8 / np.pi ** 2) < 1e-6 * 66.4
+    for c in (2 * 5000, 2 * 5001):
+        assert abs(P2[0, c] - 81.92 * 4 / np.pi ** 2) < 2e-4 * 33.2
+
+
+def test_interbin_integer_tone_halves_into_both_neighbours():
+    # a tone on bin 5000 has A_k = 0 at every other bin, so both half-bin
+    # columns next to it hold exactly |A_5000|^2 / 2
+    n, a = 1 << 17, 0.05
+    x = a * np.cos(2 * np.pi * 5000 * np.arange(n) / n + 0.7)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    P2 = o.interbin_plane(s, [0.0])
+    assert abs(P2[0, 2 * 5000] - 81.92) < 1e-9
+    assert abs(P2[0, 2 * 5000 - 1] - 40.96) < 1e-9 and abs(P2[0, 2 * 5000 + 1] - 40.96) < 1e-9
+    # the even columns are the plain plane
+    assert np.array_equal(P2[0, 0::2], o.power_plane(s, [0.0])[0])
+    P2[0, 2 * 5000 - 1: 2 * 5000 + 2] = 0
+    assert P2.max() < 1e-18
+
+
+@pytest.mark.parametrize("z", [20.0, -60.0, 96.0])
+def test_interbin_accelerated_midway_chirp(z):
+    # the template autocorrelation is exp(-i pi d) sinc(d) at every z, so a chirp
+    # whose mean frequency is midway between bins gives (8/pi^2) E(z) of the
+    # peak in its half-bin column, to the truncation of the templates
+    n, a = 1 << 17, 0.05
+    x = synth.chirp(n, synth.Injection(a, 5000.5 - z / 2, z, 0.2))
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    E = o.template_energy([z])[0]
+    P2 = o.interbin_plane(s, [z])
+    assert abs(P2[0, 2 * 5000 + 1] / (81.92 * 8 / np.pi ** 2 * E) - 1) < 5e-3
+
+
+def test_interbin_noise_has_unit_mean_exponential_power():
+    x = synth.make_series(1 << 18, [], 11, 0)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=1 << 18)
+    P2 = o.interbin_plane(s, np.array([-96.0, -41.0, 0.0, 17.0, 96.0]))
+    half = P2[:, 401:-400:2]
+    assert np.all(np.abs(half.mean(axis=1) - 1) < 0.015)
+    assert np.all(np.abs((half > 3).mean(axis=1) - math.exp(-3)) < 0.003)
+
+
+def test_interbin_search_finds_a_midway_tone_the_bin_search_misses():
+    # peak power 40: midway between bins each bin keeps 0.405 x 40 = 16.2 and
+    # the half-bin 0.81 x 40 = 32.4, against tau_1 = 20.74 (noise-free)
+    n = 1 << 17
+    a = math.sqrt(4 * 40.0 / n)
+    x = a * np.cos(2 * np.pi * 7000.5 * np.arange(n) / n + 1.1)
+    s = o.normalise(o.spectrum(x), "variance", n_samples=n)
+    zs = np.array([0.0])
+    assert o.search(o.power_plane(s, zs), zs, 2, r_lo=24, h_max=24) == []
+    c = o.search(o.interbin_plane(s, zs), zs, 2, r_lo=24, h_max=24, res=2)
+    best = max(c, key=lambda k: k.sigma)
+    assert (best.harm, best.R, best.r) == (1, 14001, 7000.5)
+    assert abs(best.power - 40 * 8 / np.pi ** 2) < 1e-3
+    # every record lies on the tone or on the cells whose harmonics reach it
+    assert all(k.harm == 1 and k.R == 14001 or k.harm == 2 and abs(k.R - 28002) <= 1 for k in c)
+
+
 # ---------------------------------------------------------- harmonic sums
 
 def _plane_from_formula(nz, nb):
