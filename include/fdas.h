@@ -83,10 +83,30 @@ typedef struct {
   double sigma_threshold;    /* Gaussian-equivalent detection threshold (default 6) */
   int32_t r_lo;              /* lowest fundamental bin searched; 0 means h_max */
   int32_t templates_per_tile; /* templates one wavefront runs per loaded segment; 0 = automatic */
+  int32_t interbin;          /* 0: plane at bin resolution; 1: half-bin plane (below) */
+  int32_t reserved;          /* must be 0 */
 } fdas_params;
 
+/* Half-bin plane (interbin = 1; the paper works at whole bins, this sub-bin
+ * step is an addition).  After the matched filter a signal at mean frequency
+ * rbar leaves y(r) proportional to exp(-i pi d) sinc(d), d = r - rbar, at every
+ * z (the template autocorrelation, by Parseval), so a signal midway between
+ * bins keeps only sinc(1/2)^2 = 0.405 of its power in either.  The half-bin
+ * value |y_r - y_{r+1}|^2 / 2 keeps 8/pi^2 = 0.81 of it, and has unit-mean
+ * noise like the bins (neighbouring outputs are uncorrelated).  With it on:
+ *  - the plane of series i has 2 N_i/2 = N_i columns per trial and starts at
+ *    element 2 Z S_i; column 2r holds P[j][r], column 2r+1 the half-bin power
+ *    between r and r+1 (y(N_i/2) from the zero-extended spectrum);
+ *  - U = L - 2 h_max - 1, so every segment holds y at its last output + 1;
+ *  - fdas_harmonic_sum works on half-bin columns: R counts half bins, a cell
+ *    is searched at stage H' if R >= 2 H' r_lo and R < 2 (N/2 - h_max), and
+ *    the record's r = R / (2H) bins;
+ *  - fdas_cluster's radius_r counts half bins;
+ *  - plane buffers must be aligned to two plane elements (8 bytes for F32). */
+
 /* One detection: 32 bytes. harm is the number of harmonics summed (H), R and j
- * the cell of the H-th harmonic (bin, acceleration-trial index), r = R/H and
+ * the cell of the H-th harmonic (bin, or half bin on a half-bin plane;
+ * acceleration-trial index), r = R/H bins (R/(2H) on a half-bin plane) and
  * z = z_j/H the fundamental, power the harmonic sum S_H, sigma its
  * Gaussian-equivalent significance. */
 typedef struct {
@@ -101,7 +121,8 @@ fdas_status fdas_default_params(fdas_params *p);
 
 /* Validates *params and creates a plan bound to `device` and the HIP stream
  * `hip_stream` (NULL = default stream).  Derived sizes: Z = (z_max - z_min)/z_step + 1,
- * h_max = ceil(z_max/2) + m, U = L - 2 h_max outputs per segment.  Thresholds
+ * h_max = ceil(z_max/2) + m, U = L - 2 h_max outputs per segment (one fewer on
+ * a half-bin plane).  Thresholds
  * tau_H solve P(Gamma(H,1) > tau_H) = P(N(0,1) > sigma_threshold) in FP64: a
  * noise harmonic sum of H unit-mean exponential powers is Gamma(H,1).
  * On failure *out is NULL and the message is available from fdas_last_error(NULL). */
@@ -139,8 +160,9 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
  * forward FFT per segment, then for every template j: product with T_j,
  * inverse FFT, and P[j][s U + i] = |y[h_max + i]|^2 for i < U, i.e.
  *   P[j][r] = | sum_{q=-h_max}^{h_max} A'_{r+q} t_q(z_j) |^2,
- * written to plane_out (plane_dtype, packed z-major).  plane_bytes is the
- * size of plane_out and must cover the whole batch. */
+ * written to plane_out (plane_dtype, packed z-major; with interbin the
+ * half-bin plane described at fdas_params).  plane_bytes is the size of
+ * plane_out and must cover the whole batch. */
 fdas_status fdas_convolve_spectrum(fdas_plan_t plan, const void *spectrum, const int64_t *lengths_host,
                                    int32_t n_series, void *plane_out, int64_t plane_bytes);
 
@@ -159,7 +181,8 @@ fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *
  * stage.  Records are appended at atomically reserved indices of `cands`
  * (device, `capacity` records, order not deterministic); *d_count (device
  * int64, zeroed by the caller before the first call of a search) counts every
- * passing cell, also those that did not fit. */
+ * passing cell, also those that did not fit.  On a half-bin plane the same
+ * sums run over half-bin columns (see fdas_params). */
 fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t *lengths_host,
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);
@@ -238,7 +261,8 @@ fdas_status fdas_copy_thresholds(fdas_plan_t plan, double *tau_host);
  * passing cells around its peak.  Record i (i < min(*d_count, capacity)) gets
  * keep[i] = 1 when no record of the same series with |R' - R| <= radius_r and
  * |j' - j| <= radius_j has a larger sigma (equal sigma: the record with the
- * smaller (j, R) wins), else 0.  cands: the records (device, with sigma filled
+ * smaller (j, R) wins), else 0 (R in the records' units: half bins after a
+ * half-bin search).  cands: the records (device, with sigma filled
  * as those calls leave them); d_count: device int64 record count; keep:
  * device uint8 [capacity]; scratch: caller-owned device memory of at least
  * fdas_cluster_scratch_bytes(capacity) bytes, 8-byte aligned, overwritten.

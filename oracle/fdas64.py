@@ -366,6 +366,22 @@ def power_cells(a_norm: np.ndarray, taps: np.ndarray, rows: np.ndarray, cols: np
     return out
 
 
+def interbin_cells(a_norm: np.ndarray, taps: np.ndarray, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """Columns of the half-bin plane (interbin_plane) at individual cells by the
+    direct sum: column c = 2r is |y(r)|^2, c = 2r + 1 is |y(r) - y(r + 1)|^2 / 2."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols, dtype=np.int64)
+    out = np.empty(len(rows))
+    for j in np.unique(rows):
+        sel = rows == j
+        r = cols[sel] // 2
+        y0 = correlate_direct(a_norm, taps[j], r)
+        y1 = correlate_direct(a_norm, taps[j], r + 1)
+        d = y0 - y1
+        out[sel] = np.where(cols[sel] % 2 == 0, y0.real ** 2 + y0.imag ** 2, 0.5 * (d.real ** 2 + d.imag ** 2))
+    return out
+
+
 # --------------------------------------------------------------- harmonic sum
 
 

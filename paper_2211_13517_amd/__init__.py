@@ -8,7 +8,8 @@ Layouts (see include/fdas.h):
   * series: float32 1-D device tensor, series i at offsets[i], length lengths[i]
   * spectrum: packed complex bins; F32 -> float32 [bins, 2], BF16 -> bfloat16
     [bins, 2], F16 -> float16 [bins, 2] (re, im)
-  * plane: packed z-major power planes, F32/BF16/F16 1-D
+  * plane: packed z-major power planes, F32/BF16/F16 1-D (two columns per
+    bin, bin then half bin, for plans made with interbin=1)
   * candidates: int32 [capacity, 8] (series, harm, R, j, then r, z, power,
     sigma as float32 bits); ``candidates_to_numpy`` decodes them.
 """
@@ -44,7 +45,7 @@ class Params(ctypes.Structure):
                 ("n_harmonics", c_int32), ("kernel_margin", c_int32), ("segment_len", c_int32),
                 ("store_dtype", c_int32), ("plane_dtype", c_int32), ("norm", c_int32),
                 ("norm_block", c_int32), ("noise_var", c_double), ("sigma_threshold", c_double),
-                ("r_lo", c_int32), ("templates_per_tile", c_int32)]
+                ("r_lo", c_int32), ("templates_per_tile", c_int32), ("interbin", c_int32), ("reserved", c_int32)]
 
 
 EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace", "fdas_make_templates",
@@ -151,7 +152,10 @@ class Plan:
         ws, L, hmax, Z = c_int64(), c_int32(), c_int32(), c_int32()
         self._check(self.lib.fdas_query(h, byref(ws), byref(L), byref(hmax), byref(Z)))
         self.ws_bytes, self.L, self.hmax, self.Z = ws.value, L.value, hmax.value, Z.value
-        self.U = self.L - 2 * self.hmax
+        # columns per bin of the plane: 2 on a half-bin (interbinned) plane,
+        # which also gives up one output per segment
+        self.res = 2 if p.interbin else 1
+        self.U = self.L - 2 * self.hmax - (1 if p.interbin else 0)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self._check(self.lib.fdas_set_workspace(h, c_void_p(self.workspace.data_ptr()), self.ws_bytes))
         self.store_dtype, self.plane_dtype = p.store_dtype, p.plane_dtype
@@ -206,7 +210,8 @@ class Plan:
 
     def new_plane(self, total_bins: int):
         import torch
-        return torch.empty(self.Z * total_bins, dtype=plane_torch_dtype(self.plane_dtype), device=self.device)
+        return torch.empty(self.Z * total_bins * self.res, dtype=plane_torch_dtype(self.plane_dtype),
+                           device=self.device)
 
     def spectrum(self, series, offsets: Sequence[int], lengths: Sequence[int], out=None):
         total = int(sum(lengths)) // 2

@@ -67,6 +67,7 @@ struct fdas_plan_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int Z = 0, j0 = 0, hmax = 0, K = 0, L = 0, U = 0, nstages = 0;
+  int res = 1;  // plane columns per bin: 2 on a half-bin plane
   double tau[5] = {0, 0, 0, 0, 0};
   int64_t max_batch = 0;
   int max_series = 0;
@@ -167,6 +168,8 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   if (!(sig > 0 && sig < 30)) return bad("sigma_threshold must be in (0, 30)");
   if (p.r_lo < 0) return bad("r_lo must be >= 0");
   if (p.templates_per_tile < 0) return bad("templates_per_tile must be >= 0");
+  if (p.interbin != 0 && p.interbin != 1) return bad("interbin must be 0 or 1");
+  if (p.reserved != 0) return bad("reserved must be 0");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return bad("invalid device");
 
@@ -185,7 +188,9 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   pl->hmax = hmax;
   pl->K = 2 * hmax + 1;
   pl->L = L;
-  pl->U = L - 2 * hmax;
+  // a half-bin plane needs y one past the last output of each segment
+  pl->res = p.interbin ? 2 : 1;
+  pl->U = L - 2 * hmax - (p.interbin ? 1 : 0);
   pl->nstages = log2i(p.n_harmonics) + 1;
   if (pl->p.r_lo == 0) pl->p.r_lo = hmax;
   for (int i = 0; i < pl->nstages; ++i) pl->tau[i] = threshold_for(1 << i, sig);
@@ -315,7 +320,7 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
     // W tile owners take tiles round-robin, so with T = nseg * G tiles the
     // launch lasts ceil(T/W) rounds of one tile (Z/G inverse FFTs plus the
     // segment's forward FFT): choose the G that minimises that product.
-    const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
+    const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0));
     const int64_t W = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
     double best = 1e300;
     G = 1;
@@ -335,7 +340,7 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
     SeriesDesc& d = pl->desc[i];
     d.in_off = offsets ? offsets[i] : 0;
     d.spec_off = spec;
-    d.plane_off = spec * pl->Z;
+    d.plane_off = spec * pl->Z * pl->res;
     d.nbins = (int32_t)(lengths[i] / 2);
     d.nseg = (int32_t)((d.nbins + pl->U - 1) / pl->U);
     d.tile_begin = tiles;
@@ -408,10 +413,40 @@ static fdas_status run_spectrum(fdas_plan_t pl, const float* series, void* spec_
   return FDAS_OK;
 }
 
+// Bytes of the packed planes of the current batch.
+static int64_t plane_need(fdas_plan_t pl) { return pl->total_bins * pl->Z * pl->res * rbytes(pl->p.plane_dtype); }
+
+// Harmonic-sum arguments for the current batch; on a half-bin plane the bin
+// limits are given in half bins.
+static HarmArgs harm_args(fdas_plan_t pl, const void* plane, fdas_candidate* cands, int64_t capacity,
+                          int64_t* d_count) {
+  HarmArgs a;
+  a.plane = plane;
+  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
+  a.cands = cands;
+  a.count = reinterpret_cast<unsigned long long*>(d_count);
+  a.capacity = capacity;
+  for (int i = 0; i < 5; ++i) a.tau[i] = i < pl->nstages ? (float)pl->tau[i] : 0.f;
+  a.z_min = pl->p.z_min;
+  a.z_step = pl->p.z_step;
+  a.n_series = (int)pl->desc.size();
+  a.Z = pl->Z;
+  a.j0 = pl->j0;
+  a.n_harm = pl->p.n_harmonics;
+  a.r_lo = pl->p.r_lo * pl->res;
+  a.hmax = pl->hmax * pl->res;
+  a.res_shift = pl->res == 2 ? 1 : 0;
+  a.max_bins = (int32_t)(pl->max_bins * pl->res);
+  return a;
+}
+
 static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64_t plane_bytes) {
   if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
-  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
+  const int64_t need = plane_need(pl);
   if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  // a half-bin plane is written as (bin, half-bin) pairs
+  if (((uintptr_t)plane) % (uintptr_t)(rbytes(pl->p.plane_dtype) * pl->res))
+    return pl->fail(FDAS_ERR_ARG, "plane must be aligned to its element size (twice that on a half-bin plane)");
   ConvArgs a;
   a.spec = spec;
   a.tspec = pl->ws + pl->off_tspec;
@@ -427,10 +462,10 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   // The grid is exactly what is resident at once: tiles are dealt
   // round-robin, so a block that had to wait for a slot would finish last.
   const int per_block = conv_waves_per_block(pl->L);
-  const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype));
+  const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0));
   const int64_t blocks_needed = pl->L == 1024 ? (pl->n_tiles + per_block - 1) / per_block : pl->n_tiles;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)pl->cu_count * per_cu));
-  hipError_t e = launch_conv(pl->L, pl->p.store_dtype, pl->p.plane_dtype, a, grid, pl->stream);
+  hipError_t e = launch_conv(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0, a, grid, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "convolve");
   return FDAS_OK;
 }
@@ -471,8 +506,7 @@ fdas_status fdas_convolve(fdas_plan_t pl, const float* series, const int64_t* of
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
   fdas_status s = set_batch(pl, offsets, lengths, n);
   if (s != FDAS_OK) return s;
-  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
-  if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  if (!plane || plane_bytes < plane_need(pl)) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
   void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
   if ((s = run_spectrum(pl, series, spec)) != FDAS_OK) return s;
   return run_conv(pl, spec, plane, plane_bytes);
@@ -488,22 +522,8 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
   fdas_status s = ensure_lengths(pl, lengths, n);
   if (s != FDAS_OK) return s;
-  HarmArgs a;
-  a.plane = plane;
-  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
-  a.cands = cands;
-  a.count = reinterpret_cast<unsigned long long*>(d_count);
-  a.capacity = capacity;
-  for (int i = 0; i < 5; ++i) a.tau[i] = i < pl->nstages ? (float)pl->tau[i] : 0.f;
-  a.z_min = pl->p.z_min;
-  a.z_step = pl->p.z_step;
-  a.n_series = n;
-  a.Z = pl->Z;
-  a.j0 = pl->j0;
-  a.n_harm = pl->p.n_harmonics;
-  a.r_lo = pl->p.r_lo;
-  a.hmax = pl->hmax;
-  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
+  const HarmArgs a = harm_args(pl, plane, cands, capacity, d_count);
+  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "harmonic sum");
   return FDAS_OK;
 }
@@ -518,22 +538,8 @@ static fdas_status enqueue_search(fdas_plan_t pl, const float* series, void* spe
   fdas_status s = run_spectrum(pl, series, spec);
   if (s != FDAS_OK) return s;
   if ((s = run_conv(pl, spec, plane, plane_bytes)) != FDAS_OK) return s;
-  HarmArgs a;
-  a.plane = plane;
-  a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
-  a.cands = cands;
-  a.count = reinterpret_cast<unsigned long long*>(d_count);
-  a.capacity = capacity;
-  for (int i = 0; i < 5; ++i) a.tau[i] = i < pl->nstages ? (float)pl->tau[i] : 0.f;
-  a.z_min = pl->p.z_min;
-  a.z_step = pl->p.z_step;
-  a.n_series = (int)pl->desc.size();
-  a.Z = pl->Z;
-  a.j0 = pl->j0;
-  a.n_harm = pl->p.n_harmonics;
-  a.r_lo = pl->p.r_lo;
-  a.hmax = pl->hmax;
-  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, (int)pl->max_bins, pl->stream)) != hipSuccess)
+  const HarmArgs a = harm_args(pl, plane, cands, capacity, d_count);
+  if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "harmonic sum");
   return FDAS_OK;
 }
@@ -554,8 +560,7 @@ fdas_status fdas_search(fdas_plan_t pl, const float* series, const int64_t* offs
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
   fdas_status s = set_batch(pl, offsets, lengths, n);  // uploads descriptors outside any capture
   if (s != FDAS_OK) return s;
-  const int64_t need = pl->total_bins * pl->Z * rbytes(pl->p.plane_dtype);
-  if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
+  if (!plane || plane_bytes < plane_need(pl)) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
   void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
   if (!use_graph) return enqueue_search(pl, series, spec, plane, plane_bytes, cands, capacity, d_count);
 
@@ -623,7 +628,7 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
       }
       const int64_t nb = p.n_samples / 2;
       const int64_t spec_bytes = align256(nb * cbytes(p.store_dtype));
-      const int64_t plane_bytes = align256(nb * pl->Z * rbytes(p.plane_dtype));
+      const int64_t plane_bytes = align256(nb * pl->Z * pl->res * rbytes(p.plane_dtype));
       const int64_t need = pl->total + spec_bytes + plane_bytes;
       if (need > scratch_bytes) {
         g_plan_error = "autotune scratch too small: need " + std::to_string(need) + " bytes";

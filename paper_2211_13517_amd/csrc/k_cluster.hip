@@ -16,7 +16,8 @@ namespace fdas {
 constexpr unsigned long long kEmpty = ~0ull;
 
 __device__ __forceinline__ unsigned long long cell_key(int series, int j, int R) {
-  return ((unsigned long long)series << 34) | ((unsigned long long)j << 22) | (unsigned long long)R;
+  // R < 2^23 (half-bin cells of a 2^22-bin series), j < 2^12
+  return ((unsigned long long)series << 35) | ((unsigned long long)j << 23) | (unsigned long long)R;
 }
 
 __device__ __forceinline__ uint32_t cell_slot(unsigned long long key, int log2t) {
@@ -61,7 +62,7 @@ __global__ void k_cluster_peaks(const fdas_candidate* __restrict__ c, const unsi
       for (int dr = -rr; dr <= rr && peak; ++dr) {
         // cells off the key's range hold no record (and must not alias one)
         if ((dj == 0 && dr == 0) || me.j + dj < 0 || me.R + dr < 0 || me.j + dj >= (1 << 12) ||
-            me.R + dr >= (1 << 22))
+            me.R + dr >= (1 << 23))
           continue;
         const unsigned long long key = cell_key(me.series, me.j + dj, me.R + dr);
         uint32_t h = cell_slot(key, log2t);

@@ -9,6 +9,14 @@
 // every tile), runs the inverse FFT and stores |y|^2 of the U = L - 2 h_max
 // outputs free of wrap-around, at plane[j][s U + i].
 //
+// Half-bin plane: U = L - 2 h_max - 1, so output i + 1 is free of wrap-around
+// too, and each output stores the pair (|y_i|^2, |y_i - y_{i+1}|^2 / 2) at
+// columns 2(s U + i) and 2(s U + i) + 1 of a row twice as long.  Output i sits
+// in thread i mod NT, register i / NT; its successor is the next lane's
+// register (a cross-lane shuffle), for the last lane of a wavefront the first
+// lane of the next wavefront (through LDS in block tiles), and for the last
+// thread of the tile the first thread's next register.
+//
 // L <= 2048: one wavefront owns a tile and exchanges through its private LDS
 // buffer, so the eight wavefronts of a block never wait for each other.
 // L = 4096, 8192: a block of L/32 threads owns a tile and synchronises.
@@ -29,8 +37,66 @@ __device__ __forceinline__ int find_series(const SeriesDesc* __restrict__ desc, 
   return lo;
 }
 
-template <class FS, int SDT, int PDT, bool BLOCK>
-__device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* xb, const c32* tw, int tid) {
+// y at output i + 1 for each of this thread's outputs i = tid + NT c (zero
+// past the tile's last point, which no valid output needs).
+template <class FS, bool BLOCK>
+__device__ __forceinline__ void next_outputs(const c32 (&v)[FS::P], c32 (&nx)[FS::P], c32* edge, int tid) {
+  constexpr int P = FS::P, NW = FS::NT / 64;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int src = (lane + 1) & 63;
+  c32 w[P];
+  static_for<0, P>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    w[c] = {__shfl(v[c].re, src, 64), __shfl(v[c].im, src, 64)};
+  });
+  if constexpr (!BLOCK) {
+    // lane 63's successor is lane 0 at the next register: w[c + 1] of lane 63
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      c32 last = {0.f, 0.f};
+      if constexpr (c + 1 < P) last = w[c + 1];
+      nx[c] = lane == 63 ? last : w[c];
+    });
+  } else {
+    if (lane == 0) {
+      static_for<0, P>([&](auto cc) { edge[wave * P + decltype(cc)::value] = v[decltype(cc)::value]; });
+    }
+    __syncthreads();
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      c32 last = {0.f, 0.f};
+      if (lane == 63) {
+        if (wave + 1 < NW) last = edge[(wave + 1) * P + c];
+        else if constexpr (c + 1 < P) last = edge[c + 1];
+      }
+      nx[c] = lane == 63 ? last : w[c];
+    });
+    // the next write to `edge` follows the barriers of the next inverse FFT
+  }
+}
+
+// A bin's power and the half-bin power after it, as one store.
+template <int PDT> struct PowerPair;
+template <> struct PowerPair<FDAS_F32> {
+  typedef float2 type;
+  __device__ __forceinline__ static type pack(float p, float h) { return make_float2(p, h); }
+};
+template <> struct PowerPair<FDAS_BF16> {
+  typedef uint32_t type;
+  __device__ __forceinline__ static type pack(float p, float h) {
+    return (uint32_t)Store<FDAS_BF16>::pack_real(p) | ((uint32_t)Store<FDAS_BF16>::pack_real(h) << 16);
+  }
+};
+template <> struct PowerPair<FDAS_F16> {
+  typedef uint32_t type;
+  __device__ __forceinline__ static type pack(float p, float h) {
+    return (uint32_t)Store<FDAS_F16>::pack_real(p) | ((uint32_t)Store<FDAS_F16>::pack_real(h) << 16);
+  }
+};
+
+template <class FS, int SDT, int PDT, bool BLOCK, bool IB>
+__device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* xb, const c32* tw, int tid,
+                                          c32* edge) {
   using SS = Store<SDT>;
   using PS = Store<PDT>;
   using CT = typename SS::cplx_t;
@@ -80,16 +146,31 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
       v[c] = cmul(F[c], SS::unpack(tc[c]));
     });
     fft_run<FS, 1, BLOCK>(v, xb, tw, tid);
-    // this thread's output i = tid + NT c lands at bin r0 + i of row t: one
-    // 64-bit pointer per template, the register index as an immediate offset
-    RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + tid);
-    static_for<0, P>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      // the register is out of range for every thread: skip (uniform branch)
-      if (NT * c + NT - 1 < lo || NT * c >= hi) return;
-      const int i = tid + NT * c;
-      if (i >= lo && i < hi) dst[NT * c] = PS::pack_real(cnorm(v[c]));
-    });
+    if constexpr (IB) {
+      c32 nx[P];
+      next_outputs<FS, BLOCK>(v, nx, edge, tid);
+      using PP = PowerPair<PDT>;
+      typename PP::type* dst =
+          reinterpret_cast<typename PP::type*>(out + (size_t)t * (2u * (uint32_t)d.nbins)) + (r0 + tid);
+      static_for<0, P>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (NT * c + NT - 1 < lo || NT * c >= hi) return;
+        const int i = tid + NT * c;
+        const c32 dv = {v[c].re - nx[c].re, v[c].im - nx[c].im};
+        if (i >= lo && i < hi) dst[NT * c] = PP::pack(cnorm(v[c]), 0.5f * cnorm(dv));
+      });
+    } else {
+      // this thread's output i = tid + NT c lands at bin r0 + i of row t: one
+      // 64-bit pointer per template, the register index as an immediate offset
+      RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + tid);
+      static_for<0, P>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        // the register is out of range for every thread: skip (uniform branch)
+        if (NT * c + NT - 1 < lo || NT * c >= hi) return;
+        const int i = tid + NT * c;
+        if (i >= lo && i < hi) dst[NT * c] = PS::pack_real(cnorm(v[c]));
+      });
+    }
     static_for<0, P>([&](auto cc) { tc[decltype(cc)::value] = tn[decltype(cc)::value]; });
   }
 }
@@ -103,7 +184,7 @@ using ConvShape = FftShape<L, 16, 16>;
 
 // Two wavefronts per SIMD: with the template prefetch in registers a third
 // wavefront (possible for 16-bit storage) measured no faster.
-template <int L, int SDT, int PDT>
+template <int L, int SDT, int PDT, bool IB>
 __global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(2)))
 void k_conv_wave(ConvArgs a) {
   using FS = ConvShape<L>;
@@ -115,96 +196,96 @@ void k_conv_wave(ConvArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * kConvWaves;
   for (int64_t tile = (int64_t)blockIdx.x * kConvWaves + wave; tile < a.n_tiles; tile += nw)
-    conv_tile<FS, SDT, PDT, false>(a, tile, xb[wave], tw, lane);
+    conv_tile<FS, SDT, PDT, false, IB>(a, tile, xb[wave], tw, lane, nullptr);
 }
 
-template <int L, int SDT, int PDT>
+template <int L, int SDT, int PDT, bool IB>
 __global__ __launch_bounds__(ConvShape<L>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_block(ConvArgs a) {
   using FS = ConvShape<L>;
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[FS::XBUF];
+  __shared__ c32 edge[IB ? FS::NT / 64 * FS::P : 1];  // first lane's outputs of each wavefront
   stage_table(tw, a.tw, FS::TW_SIZE);
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
-    conv_tile<FS, SDT, PDT, true>(a, tile, xb, tw, threadIdx.x);
+    conv_tile<FS, SDT, PDT, true, IB>(a, tile, xb, tw, threadIdx.x, edge);
 }
 
 int conv_waves_per_block(int L) { return L == 1024 ? kConvWaves : L / 16 / 64; }
 
-template <int L, int SDT, int PDT>
+template <int L, int SDT, int PDT, bool IB>
 static void conv_launch(const ConvArgs& a, int grid, hipStream_t st) {
   if constexpr (ConvShape<L>::NT == 64)
-    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT>), dim3(grid), dim3(64 * kConvWaves), 0, st, a);
+    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT, IB>), dim3(grid), dim3(64 * kConvWaves), 0, st, a);
   else
-    hipLaunchKernelGGL((k_conv_block<L, SDT, PDT>), dim3(grid), dim3(ConvShape<L>::NT), 0, st, a);
+    hipLaunchKernelGGL((k_conv_block<L, SDT, PDT, IB>), dim3(grid), dim3(ConvShape<L>::NT), 0, st, a);
 }
 
-template <int L, int SDT, int PDT>
+template <int L, int SDT, int PDT, bool IB>
 static int occ() {
   int n = 0;
   hipError_t e;
   if constexpr (ConvShape<L>::NT == 64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT>, 64 * kConvWaves, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT, IB>, 64 * kConvWaves, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT>, ConvShape<L>::NT, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT, IB>, ConvShape<L>::NT, 0);
   if (e != hipSuccess) n = 1;
   return n;
 }
 
-template <int L>
-static int occ_l(int sdt, int pdt) {
-  auto sel = [&](auto sd) -> int {
-    constexpr int S = decltype(sd)::value;
-    switch (pdt) {
-      case FDAS_F32: return occ<L, S, FDAS_F32>();
-      case FDAS_BF16: return occ<L, S, FDAS_BF16>();
-      default: return occ<L, S, FDAS_F16>();
-    }
-  };
-  switch (sdt) {
-    case FDAS_F32: return sel(std::integral_constant<int, FDAS_F32>{});
-    case FDAS_BF16: return sel(std::integral_constant<int, FDAS_BF16>{});
-    default: return sel(std::integral_constant<int, FDAS_F16>{});
+// Calls f(integral_constant<int, dt>) for a storage type known at run time.
+template <class F>
+static auto with_dtype(int dt, F&& f) {
+  switch (dt) {
+    case FDAS_F32: return f(std::integral_constant<int, FDAS_F32>{});
+    case FDAS_BF16: return f(std::integral_constant<int, FDAS_BF16>{});
+    default: return f(std::integral_constant<int, FDAS_F16>{});
   }
 }
 
-int conv_blocks_per_cu(int L, int sdt, int pdt) {
+template <int L>
+static int occ_l(int sdt, int pdt, bool ib) {
+  return with_dtype(sdt, [&](auto sd) {
+    return with_dtype(pdt, [&](auto pd) {
+      constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
+      return ib ? occ<L, S, Q, true>() : occ<L, S, Q, false>();
+    });
+  });
+}
+
+int conv_blocks_per_cu(int L, int sdt, int pdt, bool interbin) {
   switch (L) {
-    case 1024: return occ_l<1024>(sdt, pdt);
-    case 2048: return occ_l<2048>(sdt, pdt);
-    case 4096: return occ_l<4096>(sdt, pdt);
-    case 8192: return occ_l<8192>(sdt, pdt);
+    case 1024: return occ_l<1024>(sdt, pdt, interbin);
+    case 2048: return occ_l<2048>(sdt, pdt, interbin);
+    case 4096: return occ_l<4096>(sdt, pdt, interbin);
+    case 8192: return occ_l<8192>(sdt, pdt, interbin);
     default: return 1;
   }
 }
 
-template <int L, int SDT>
-static hipError_t conv_pdt(int pdt, const ConvArgs& a, int grid, hipStream_t st) {
-  switch (pdt) {
-    case FDAS_F32: conv_launch<L, SDT, FDAS_F32>(a, grid, st); break;
-    case FDAS_BF16: conv_launch<L, SDT, FDAS_BF16>(a, grid, st); break;
-    case FDAS_F16: conv_launch<L, SDT, FDAS_F16>(a, grid, st); break;
-    default: return hipErrorInvalidValue;
-  }
+template <int L>
+static hipError_t conv_l(int sdt, int pdt, bool ib, const ConvArgs& a, int grid, hipStream_t st) {
+  if (sdt < FDAS_F32 || sdt > FDAS_F16 || pdt < FDAS_F32 || pdt > FDAS_F16) return hipErrorInvalidValue;
+  with_dtype(sdt, [&](auto sd) {
+    with_dtype(pdt, [&](auto pd) {
+      constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
+      if (ib)
+        conv_launch<L, S, Q, true>(a, grid, st);
+      else
+        conv_launch<L, S, Q, false>(a, grid, st);
+      return 0;
+    });
+    return 0;
+  });
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t conv_sdt(int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st) {
-  switch (sdt) {
-    case FDAS_F32: return conv_pdt<L, FDAS_F32>(pdt, a, grid, st);
-    case FDAS_BF16: return conv_pdt<L, FDAS_BF16>(pdt, a, grid, st);
-    case FDAS_F16: return conv_pdt<L, FDAS_F16>(pdt, a, grid, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_conv(int L, int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st) {
+hipError_t launch_conv(int L, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st) {
   switch (L) {
-    case 1024: return conv_sdt<1024>(sdt, pdt, a, grid, st);
-    case 2048: return conv_sdt<2048>(sdt, pdt, a, grid, st);
-    case 4096: return conv_sdt<4096>(sdt, pdt, a, grid, st);
-    case 8192: return conv_sdt<8192>(sdt, pdt, a, grid, st);
+    case 1024: return conv_l<1024>(sdt, pdt, interbin, a, grid, st);
+    case 2048: return conv_l<2048>(sdt, pdt, interbin, a, grid, st);
+    case 4096: return conv_l<4096>(sdt, pdt, interbin, a, grid, st);
+    case 8192: return conv_l<8192>(sdt, pdt, interbin, a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -11,7 +11,8 @@
 // fundamental R/H' is at least r_lo and R < N/2 - h_max, passes when
 // S_H' >= tau_H', and a cell reports only its most significant passing stage
 // (smallest noise tail probability P(Gamma(H', 1) > S), evaluated in FP64 for
-// the few passing cells).
+// the few passing cells).  On a half-bin plane (two columns per bin) the same
+// rules run over columns: R, r_lo and h_max count half bins.
 #include <algorithm>
 
 #include "fft.hpp"
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   __shared__ __align__(16) RT strip[HT::SIZE];
 
   const SeriesDesc d = a.desc[blockIdx.z];
-  const int nb = d.nbins;
+  const int nb = d.nbins << a.res_shift;  // plane columns of the series
   const int ncol = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
   const int tile = xcd_tile(blockIdx.x);
   const int grp = tile / (ncol * G), inner = tile % (ncol * G);
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
       c.harm = hh;
       c.R = R;
       c.j = j;
-      c.r = (float)((double)R / hh);
+      c.r = (float)((double)R / (hh << a.res_shift));
       c.z = (float)((a.z_min + a.z_step * j) / hh);
       c.power = S[bi];
       c.sigma = 0.f;  // filled in by k_cand_sigma
@@ -418,9 +419,8 @@ static hipError_t hs_h(const HarmArgs& a, dim3 g, hipStream_t st) {
 }
 
 // The x-grid covers the longest series; blocks past a shorter series' end exit.
-hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st) {
-  HarmArgs b = a;
-  b.max_bins = max_bins;
+hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, hipStream_t st) {
+  const HarmArgs& b = a;
   const dim3 g(1, 1, a.n_series);
   hipError_t e;
   switch (pdt) {

@@ -66,9 +66,10 @@ struct ConvArgs {
   int64_t n_tiles;         // sum over series of nseg * G
   int32_t n_series, Z, G, U, hmax;
 };
-hipError_t launch_conv(int L, int sdt, int pdt, const ConvArgs& a, int grid, hipStream_t st);
+// interbin: also write the half-bin power between each output and the next
+hipError_t launch_conv(int L, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st);
 int conv_waves_per_block(int L);
-int conv_blocks_per_cu(int L, int sdt, int pdt);  // resident blocks per CU (occupancy query)
+int conv_blocks_per_cu(int L, int sdt, int pdt, bool interbin);  // resident blocks per CU (occupancy query)
 
 // harmonic sums
 struct HarmArgs {
@@ -79,10 +80,14 @@ struct HarmArgs {
   int64_t capacity;
   float tau[5];
   double z_min, z_step;
+  // plane columns: a series of nbins bins has nbins << res_shift columns
+  // (res_shift 1 on a half-bin plane); r_lo, hmax and max_bins are given in
+  // columns
   int32_t n_series, Z, j0, n_harm, r_lo, hmax;
+  int32_t res_shift;
   int32_t max_bins;  // longest series in the batch (sets the tile grid)
 };
-hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, int max_bins, hipStream_t st);
+hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, hipStream_t st);
 
 // off-grid power and refinement
 hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,

@@ -39,8 +39,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_the_header(lib):
-    # fdas_params: 2 int64 + 4 double + 7 int32 (+4 pad) + 2 double + 2 int32
-    assert ctypes.sizeof(fdas.Params) == 8 * 6 + 4 * 7 + 4 + 8 * 2 + 4 * 2
+    # fdas_params: 2 int64 + 4 double + 7 int32 (+4 pad) + 2 double + 4 int32
+    assert ctypes.sizeof(fdas.Params) == 8 * 6 + 4 * 7 + 4 + 8 * 2 + 4 * 4
 
 
 def test_default_params(lib):
@@ -64,6 +64,8 @@ BAD = [
     dict(norm_block=1000),
     dict(sigma_threshold=-1.0),
     dict(max_batch_samples=1 << 10),
+    dict(interbin=2),
+    dict(reserved=1),
 ]
 
 

@@ -347,6 +347,19 @@ def test_interbin_noise_has_unit_mean_exponential_power():
     assert np.all(np.abs((half > 3).mean(axis=1) - math.exp(-3)) < 0.003)
 
 
+def test_interbin_cells_direct_sum_agrees_with_whole_plane():
+    rng = np.random.default_rng(12)
+    n = 1 << 12
+    a = rng.standard_normal(n // 2) + 1j * rng.standard_normal(n // 2)
+    zs = o.z_grid(-16, 16, 2)
+    taps, _ = o.template_taps(zs)
+    whole = o.interbin_plane(a, zs)
+    rows = rng.integers(0, len(zs), 400)
+    cols = rng.integers(0, n, 400)
+    cols[:4] = [0, 1, n - 2, n - 1]            # both ends of the spectrum
+    np.testing.assert_allclose(o.interbin_cells(a, taps, rows, cols), whole[rows, cols], rtol=1e-10, atol=1e-10)
+
+
 def test_interbin_search_finds_a_midway_tone_the_bin_search_misses():
     # peak power 40: midway between bins each bin keeps 0.405 x 40 = 16.2 and
     # the half-bin 0.81 x 40 = 32.4, against tau_1 = 20.74 (noise-free)
