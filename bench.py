@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error/recall leg")
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement leg")
     ap.add_argument("--no-interbin", action="store_true", help="skip the half-bin plane leg")
+    ap.add_argument("--no-energy", action="store_true", help="skip the energy-counter leg")
     ap.add_argument("--n", type=int, default=1 << 23)
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 1 GiB device copy (for counters)")
     ap.add_argument("--json-out", default=None)
@@ -156,7 +157,88 @@ def run_path(fdas, torch, xt, n, args, store, plane, interbin=0):
     harm_ms = [b.elapsed_time(c) for _, b, c in evs]
     pl.check(count, cap)
     return dict(plan=pl, plane=P, spec=spec, cands=cands, count=int(count.item()), step_s=dt / args.steps,
-                conv_ms=float(np.mean(conv_ms)), harm_ms=float(np.mean(harm_ms)))
+                conv_ms=float(np.mean(conv_ms)), harm_ms=float(np.mean(harm_ms)), step=step)
+
+
+class EnergyMeter:
+    """The GPU's energy counter (accumulator x resolution in microjoules) read
+    through amdsmi, for the device torch calls cuda:0, matched by PCI address
+    (or the only device amdsmi sees).  Reads only; no clock or power control."""
+
+    def __init__(self, torch, smi=None):
+        if smi is None:
+            import amdsmi as smi
+        self.smi = smi
+        smi.amdsmi_init()
+        props = torch.cuda.get_device_properties(0)
+        want = (int(props.pci_domain_id), int(props.pci_bus_id), int(props.pci_device_id))
+        handles = list(smi.amdsmi_get_processor_handles())
+        match = []
+        for h in handles:
+            dom, bus, rest = smi.amdsmi_get_gpu_device_bdf(h).split(":")
+            if (int(dom, 16), int(bus, 16), int(rest.split(".")[0], 16)) == want:
+                match.append(h)
+        if len(match) == 1:
+            self.h, self.matched = match[0], "pci address"
+        elif len(handles) == 1:
+            self.h, self.matched = handles[0], "only device visible"
+        else:
+            raise RuntimeError(f"no unique amdsmi device for pci {want} among {len(handles)}")
+
+    def joules(self) -> float:
+        e = self.smi.amdsmi_get_energy_count(self.h)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+
+    def gfxclk_mhz(self):
+        """Graphics clock from the metrics table: the average if reported,
+        else the mean of the per-XCD current clocks (N/A fields skipped)."""
+        try:
+            m = self.smi.amdsmi_get_gpu_metrics_info(self.h)
+        except Exception:
+            return None
+        for key in ("average_gfxclk_frequency", "current_gfxclk", "current_gfxclks"):
+            v = m.get(key, "N/A")
+            vals = v if isinstance(v, (list, tuple)) else [v]
+            vals = [float(x) for x in vals if isinstance(x, (int, float)) and 0 < x < 65535]
+            if vals:
+                return sum(vals) / len(vals)
+        return None
+
+    def close(self):
+        try:
+            self.smi.amdsmi_shut_down()
+        except Exception:
+            pass
+
+
+def energy_leg(torch, meter, runs, bt, seconds=2.0):
+    """Energy per 10^12 bins x templates of the whole step for each storage
+    type, from the counter over about `seconds` of back-to-back steps, and the
+    idle power over one second before them.  Clocks are whatever the GPU
+    runs at (reported, not set)."""
+    torch.cuda.synchronize()
+    time.sleep(0.5)
+    e0, t0 = meter.joules(), time.perf_counter()
+    time.sleep(1.0)
+    e1, t1 = meter.joules(), time.perf_counter()
+    idle = (e1 - e0) / (t1 - t0)
+    out = {"idle_W": idle, "device": meter.matched, "clock_control": "none (default clocks)"}
+    for name, r in runs.items():
+        k = max(20, int(seconds / r["step_s"]))
+        r["step"]()
+        torch.cuda.synchronize()
+        e0, t0 = meter.joules(), time.perf_counter()
+        for _ in range(k):
+            r["step"]()
+        torch.cuda.synchronize()
+        e1, t1 = meter.joules(), time.perf_counter()
+        E, T = e1 - e0, t1 - t0
+        out[name] = {"steps": k, "seconds": T, "avg_W": E / T, "J_per_1e12_bt": E / (k * bt) * 1e12,
+                     "above_idle_J_per_1e12_bt": (E - idle * T) / (k * bt) * 1e12,
+                     "avg_gfxclk_MHz": meter.gfxclk_mhz()}
+    if "bf16" in out and "f32" in out:
+        out["bf16_energy_saving"] = 1.0 - out["bf16"]["J_per_1e12_bt"] / out["f32"]["J_per_1e12_bt"]
+    return out
 
 
 def midway_recall(torch, fdas, synth, runs, n, n_inj=64, p0=44.0):
@@ -542,6 +624,15 @@ def main():
         out["accuracy"] = {args.store: oracle_checks(o, synth, x, inj, res, Z)}
         if not args.no_fp32:
             out["accuracy"]["f32"] = oracle_checks(o, synth, x, inj, r32, Z)
+    if not args.no_energy and not args.no_fp32 and args.store == "bf16":
+        try:
+            meter = EnergyMeter(torch)
+            try:
+                out["energy"] = energy_leg(torch, meter, {"bf16": res, "f32": r32}, bt)
+            finally:
+                meter.close()
+        except Exception as e:  # telemetry is optional: report, do not fail the bench
+            out["energy"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_interbin:
         rib = run_path(fdas, torch, xt, n, args, args.store, plane_dt, interbin=1)
         out["interbin"] = {

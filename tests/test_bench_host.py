@@ -1,0 +1,91 @@
+"""Host-side logic of bench.py that needs no GPU: the energy counter's device
+matching and unit scaling, and the energy-per-work arithmetic."""
+import types
+
+import pytest
+
+import bench
+
+
+class FakeSmi:
+    """Two devices; the counter advances by `rate` units per fake second."""
+
+    def __init__(self, bdfs, resolution=15.3):
+        self.bdfs = bdfs
+        self.res = resolution
+        self.acc = {i: 1000 * i for i in range(len(bdfs))}
+        self.inited = False
+
+    def amdsmi_init(self):
+        self.inited = True
+
+    def amdsmi_shut_down(self):
+        self.inited = False
+
+    def amdsmi_get_processor_handles(self):
+        return list(range(len(self.bdfs)))
+
+    def amdsmi_get_gpu_device_bdf(self, h):
+        return self.bdfs[h]
+
+    def amdsmi_get_energy_count(self, h):
+        return {"energy_accumulator": self.acc[h], "counter_resolution": self.res, "timestamp": 0}
+
+    def amdsmi_get_gpu_metrics_info(self, h):
+        return {"average_gfxclk_frequency": 2400}
+
+
+def fake_torch(dom=0, bus=0x75, dev=0):
+    props = types.SimpleNamespace(pci_domain_id=dom, pci_bus_id=bus, pci_device_id=dev)
+    cuda = types.SimpleNamespace(get_device_properties=lambda i: props, synchronize=lambda: None)
+    return types.SimpleNamespace(cuda=cuda)
+
+
+def test_meter_matches_by_pci_address_and_scales_to_joules():
+    smi = FakeSmi(["0000:05:00.0", "0000:75:00.0"])
+    m = bench.EnergyMeter(fake_torch(bus=0x75), smi=smi)
+    assert m.h == 1 and m.matched == "pci address"
+    assert m.joules() == pytest.approx(1000 * 15.3e-6)
+    assert m.gfxclk_mhz() == 2400.0
+    m.close()
+    assert not smi.inited
+
+
+def test_meter_falls_back_to_the_only_device_and_refuses_ambiguity():
+    m = bench.EnergyMeter(fake_torch(bus=0x11), smi=FakeSmi(["0000:05:00.0"]))
+    assert m.h == 0 and m.matched == "only device visible"
+    with pytest.raises(RuntimeError):
+        bench.EnergyMeter(fake_torch(bus=0x11), smi=FakeSmi(["0000:05:00.0", "0000:06:00.0"]))
+
+
+def test_gfxclk_falls_back_to_per_xcd_clocks():
+    smi = FakeSmi(["0000:75:00.0"])
+    smi.amdsmi_get_gpu_metrics_info = lambda h: {"average_gfxclk_frequency": "N/A", "current_gfxclk": "N/A",
+                                                 "current_gfxclks": [2000, 2200, "N/A", 65535]}
+    assert bench.EnergyMeter(fake_torch(), smi=smi).gfxclk_mhz() == 2100.0
+
+
+def test_energy_leg_arithmetic(monkeypatch):
+    """Idle 100 W; the bf16 step draws 600 W for 1 ms, the f32 step 500 W for
+    2 ms: energy per 10^12 bt follows from the counter and the step count."""
+    clock = {"t": 0.0}
+    smi = FakeSmi(["0000:75:00.0"], resolution=1.0)       # 1 microjoule per unit
+    meter = bench.EnergyMeter(fake_torch(), smi=smi)
+
+    def advance(seconds, watts):
+        clock["t"] += seconds
+        smi.acc[0] += int(round(watts * seconds * 1e6))
+
+    monkeypatch.setattr(bench.time, "sleep", lambda s: advance(s, 100.0))
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    runs = {"bf16": {"step_s": 1e-3, "step": lambda: advance(1e-3, 600.0)},
+            "f32": {"step_s": 2e-3, "step": lambda: advance(2e-3, 500.0)}}
+    bt = 8.1e8
+    out = bench.energy_leg(fake_torch(), meter, runs, bt, seconds=0.1)
+    assert out["idle_W"] == pytest.approx(100.0)
+    assert out["bf16"]["steps"] == 100 and out["f32"]["steps"] == 50
+    assert out["bf16"]["avg_W"] == pytest.approx(600.0)
+    assert out["bf16"]["J_per_1e12_bt"] == pytest.approx(0.6 / bt * 1e12)
+    assert out["f32"]["J_per_1e12_bt"] == pytest.approx(1.0 / bt * 1e12)
+    assert out["f32"]["above_idle_J_per_1e12_bt"] == pytest.approx(0.8 / bt * 1e12)
+    assert out["bf16_energy_saving"] == pytest.approx(0.4)
