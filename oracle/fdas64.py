@@ -661,6 +661,77 @@ def refine_optimum(a: np.ndarray, r0: float, z0: float, margin: int = 16,
     return r, z, p
 
 
+def rz_power_harmonics(a: np.ndarray, r: float, z: float, n_harm: int, margin: int = 16) -> float:
+    """S(r, z) = sum_{k=1}^{n_harm} P(k r, k z): the incoherent sum over the
+    harmonics of a fundamental at (r, z).  Harmonic k of a signal whose
+    frequency drifts by z bins over the observation lies at k times its
+    frequency and drifts by k z (READING: refinement of a harmonic-sum
+    candidate maximises the same sum off the grid)."""
+    return float(sum(rz_power(a, k * r, k * z, margin) for k in range(1, n_harm + 1)))
+
+
+def rz_power_harmonics_grad(a: np.ndarray, r: float, z: float, n_harm: int, margin: int = 16):
+    """S with dS/dr = sum_k k dP/dr(k r, k z) and dS/dz = sum_k k dP/dz(k r, k z)."""
+    S = gr = gz = 0.0
+    for k in range(1, n_harm + 1):
+        p, dr, dz, _, _ = rz_power_grad(a, k * r, k * z, margin)
+        S += p
+        gr += k * dr
+        gz += k * dz
+    return S, gr, gz
+
+
+def refine_harmonic_optimum(a: np.ndarray, r0: float, z0: float, n_harm: int, margin: int = 16,
+                            polish: int = 8, max_moves: int = 8):
+    """Oracle local maximum of S(r, z) near the fundamental (r0, z0): the grid
+    search of refine_optimum with window and steps divided by n_harm (the
+    top harmonic moves n_harm times as fast; steps 0.02/n_harm bin and
+    0.04/n_harm z), re-centred until its best point is interior, then Newton
+    steps on the FP64 gradient with a finite-difference Hessian."""
+    H = n_harm
+    dr, dz, step_r, step_z = 0.6 / H, 1.2 / H, 0.02 / H, 0.04 / H
+    rc, zc = r0, z0
+    for _ in range(max_moves):
+        rs = rc + np.arange(-dr, dr + 1e-12, step_r)
+        zs = zc + np.arange(-dz, dz + 1e-12, step_z)
+        best = (-1.0, rc, zc)
+        edge = False
+        for iz, z in enumerate(zs):
+            for ir, r in enumerate(rs):
+                p = rz_power_harmonics(a, r, z, H, margin)
+                if p > best[0]:
+                    best = (p, r, z)
+                    edge = ir in (0, len(rs) - 1) or iz in (0, len(zs) - 1)
+        if not edge:
+            break
+        rc, zc = best[1], best[2]
+    p, r, z = best
+    for _ in range(polish):
+        _, gr, gz = rz_power_harmonics_grad(a, r, z, H, margin)
+        e = 1e-4 / H
+        g_rp = rz_power_harmonics_grad(a, r + e, z, H, margin)
+        g_rm = rz_power_harmonics_grad(a, r - e, z, H, margin)
+        g_zp = rz_power_harmonics_grad(a, r, z + e, H, margin)
+        g_zm = rz_power_harmonics_grad(a, r, z - e, H, margin)
+        hrr = (g_rp[1] - g_rm[1]) / (2 * e)
+        hzz = (g_zp[2] - g_zm[2]) / (2 * e)
+        hrz = 0.5 * ((g_rp[2] - g_rm[2]) / (2 * e) + (g_zp[1] - g_zm[1]) / (2 * e))
+        det = hrr * hzz - hrz * hrz
+        if not (hrr < 0 and det > 0):
+            break
+        sr = -(hzz * gr - hrz * gz) / det
+        sz = -(-hrz * gr + hrr * gz) / det
+        if abs(sr) > 0.05 / H or abs(sz) > 0.1 / H:
+            break
+        pn = rz_power_harmonics(a, r + sr, z + sz, H, margin)
+        if pn < p:
+            break
+        r, z, p = r + sr, z + sz, pn
+        if abs(sr) < 1e-9 and abs(sz) < 1e-9:
+            break
+    return r, z, p
+
+
 # ---------------------------------------------------------------- error metrics
 
 

@@ -561,6 +561,55 @@ def test_rz_gradients_match_central_differences():
             assert abs(ga[idx] - (dre + 1j * dim)) < 1e-5 * max(1, abs(ga[idx]))
 
 
+def _harmonic_train(n, rbar, z, amps, phase=0.4):
+    """Noise-free signal whose harmonic k sits at k rbar (mean) and drifts by k z."""
+    u = np.arange(n) / n
+    x = np.zeros(n)
+    for k, a in enumerate(amps, 1):
+        x += a * np.cos(2 * np.pi * (k * (rbar - z / 2) * u + 0.5 * k * z * u * u) + phase * k)
+    return x
+
+
+def test_rz_power_harmonics_of_a_noise_free_harmonic_train():
+    # S at the true fundamental: each harmonic contributes (N a_k^2 / 4) W_k^2,
+    # W_k the response energy inside its window (the matched sum of the
+    # signal's own response), harmonics far apart do not interact
+    n = 1 << 17
+    rbar, z, amps = 1003.2, 6.4, [0.03, 0.02, 0.015, 0.01]
+    s = o.normalise(o.spectrum(_harmonic_train(n, rbar, z, amps)), "variance", n_samples=n)
+    want = 0.0
+    for k, a in enumerate(amps, 1):
+        ks = o.rz_window(k * rbar, k * z)
+        W = np.sum(np.abs(o.response(ks - k * rbar, k * z)) ** 2)
+        want += n * a * a / 4 * W * W
+    assert abs(o.rz_power_harmonics(s, rbar, z, 4) / want - 1) < 5e-4
+    # one harmonic is the single-harmonic power
+    assert o.rz_power_harmonics(s, rbar, z, 1) == o.rz_power(s, rbar, z)
+
+
+def test_rz_power_harmonics_gradient_matches_central_differences():
+    n = 1 << 17
+    s = o.normalise(o.spectrum(_harmonic_train(n, 1003.2, 6.4, [0.03, 0.02, 0.015, 0.01])), "variance",
+                    n_samples=n)
+    for r, z in [(1003.23, 6.37), (1003.11, 6.52), (1002.95, 6.3)]:
+        S, gr, gz = o.rz_power_harmonics_grad(s, r, z, 4)
+        h = 1e-5
+        fr = (o.rz_power_harmonics(s, r + h, z, 4) - o.rz_power_harmonics(s, r - h, z, 4)) / (2 * h)
+        fz = (o.rz_power_harmonics(s, r, z + h, 4) - o.rz_power_harmonics(s, r, z - h, 4)) / (2 * h)
+        assert abs(gr - fr) < 1e-5 * max(1.0, S) and abs(gz - fz) < 1e-5 * max(1.0, S)
+
+
+def test_refine_harmonic_optimum_finds_the_noise_free_fundamental():
+    # k rbar and k z stay clear of the window steps (integer k r, even k z)
+    n = 1 << 17
+    rbar, z = 1003.2, 6.4
+    s = o.normalise(o.spectrum(_harmonic_train(n, rbar, z, [0.03, 0.02, 0.015, 0.01])), "variance",
+                    n_samples=n)
+    r, zz, p = o.refine_harmonic_optimum(s, rbar + 0.02, z - 0.04, 4)
+    assert abs(r - rbar) < 1e-3 and abs(zz - z) < 1e-2
+    assert p >= o.rz_power_harmonics(s, rbar, z, 4) * (1 - 1e-6)
+
+
 def test_refine_optimum_on_noise_free_signal():
     n = 1 << 17
     inj = synth.Injection(0.05, 4000.3, 14.6, 0.9)
