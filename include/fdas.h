@@ -219,6 +219,21 @@ fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n
 fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, double *r, double *z, int64_t n,
                         int32_t n_iter, double *p_final);
 
+/* Harmonic refinement: the same ascent on the incoherent harmonic power of a
+ * fundamental (r, z) (harmonic k of a signal drifting by z bins lies at k r and
+ * drifts by k z; a candidate of stage H is refined on the sum it was found
+ * with):
+ *   S(r, z) = sum_{k=1}^{H} P(k r, k z),  dS/dr = sum_k k dP/dr(k r, k z), likewise z,
+ * step (dS/dr / (2 a W), dS/dz / (2 b W)) with W = sum_k k^2 P(k r, k z),
+ * clamped to 0.25/H bin and 2/H z and halved until S grows; for H = 1 exactly
+ * fdas_refine.  n_harm: device int32 [n], H per candidate in [1, 32] (any
+ * other value leaves that candidate's r and z unchanged and sets its p_final
+ * to NaN).  r, z (double [n], fundamentals) are updated in place; p_final
+ * (double [n]) receives S in FP64 at the returned position.  n_iter = 0
+ * evaluates S at the given positions. */
+fdas_status fdas_refine_harmonics(fdas_plan_t plan, const void *spectrum, int64_t n_bins, double *r, double *z,
+                                  const int32_t *n_harm, int64_t n, int32_t n_iter, double *p_final);
+
 /* The whole search for one batch in one call: resets *d_count (with a kernel),
  * then spectrum, convolution and harmonic sums exactly as fdas_spectrum,
  * fdas_convolve_spectrum and fdas_harmonic_sum.  With use_graph != 0 the

@@ -52,7 +52,7 @@ EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace
            "fdas_spectrum", "fdas_convolve_spectrum", "fdas_convolve", "fdas_harmonic_sum", "fdas_check",
            "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
-           "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster"]
+           "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster", "fdas_refine_harmonics"]
 
 _lib = None
 
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
         "fdas_rz_power": ([P, P, c_int64, P, P, c_int64, P, P], c_int),
         "fdas_rz_power_grad": ([P, P, c_int64, P, P, P, P, c_int64, P, P, P], c_int),
         "fdas_refine": ([P, P, c_int64, P, P, c_int64, c_int32, P], c_int),
+        "fdas_refine_harmonics": ([P, P, c_int64, P, P, P, c_int64, c_int32, P], c_int),
         "fdas_search": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64, P, c_int64, P, c_int32],
                         c_int),
         "fdas_autotune": ([POINTER(Params), c_int, P, P, c_int64, POINTER(Params), POINTER(c_double)], c_int),
@@ -317,6 +318,24 @@ class Plan:
         self._check(self.lib.fdas_refine(self.handle, c_void_p(spectrum.data_ptr()), spectrum.shape[0],
                                          c_void_p(r.data_ptr()), c_void_p(z.data_ptr()), n, n_iter,
                                          c_void_p(pf.data_ptr())))
+        return r, z, pf
+
+    def refine_harmonics(self, spectrum, r, z, n_harm, n_iter: int = 30):
+        """Ascent of S = sum_{k<=H} P(k r, k z) at fundamentals (r, z), H per
+        candidate (int tensor or scalar): returns (r, z, S float64)."""
+        import torch
+        r = r.clone().contiguous().double()
+        z = z.clone().contiguous().double()
+        n = r.numel()
+        if not torch.is_tensor(n_harm):
+            n_harm = torch.full((n,), int(n_harm), dtype=torch.int32, device=self.device)
+        h = n_harm.to(device=self.device, dtype=torch.int32).contiguous()
+        if h.numel() != n:
+            raise ValueError("n_harm must hold one count per candidate")
+        pf = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._check(self.lib.fdas_refine_harmonics(self.handle, c_void_p(spectrum.data_ptr()), spectrum.shape[0],
+                                                   c_void_p(r.data_ptr()), c_void_p(z.data_ptr()),
+                                                   c_void_p(h.data_ptr()), n, n_iter, c_void_p(pf.data_ptr())))
         return r, z, pf
 
     def test_fft(self, x, direction: int):

@@ -796,6 +796,20 @@ fdas_status fdas_refine(fdas_plan_t pl, const void* spec, int64_t nb, double* r,
   return FDAS_OK;
 }
 
+fdas_status fdas_refine_harmonics(fdas_plan_t pl, const void* spec, int64_t nb, double* r, double* z,
+                                  const int32_t* n_harm, int64_t n, int32_t n_iter, double* p_final) {
+  if (!pl) return FDAS_ERR_ARG;
+  fdas_status s = rz_check(pl, spec, nb, n);
+  if (s != FDAS_OK) return s;
+  if (n == 0) return FDAS_OK;
+  if (!r || !z || !n_harm || !p_final || n_iter < 0 || n_iter > 1000)
+    return pl->fail(FDAS_ERR_ARG, "r, z, n_harm, p_final are required and 0 <= n_iter <= 1000");
+  hipError_t e = launch_refine_harmonics(pl->p.store_dtype, spec, nb, r, z, n_harm, n, n_iter, pl->p.kernel_margin,
+                                         p_final, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "refine harmonics");
+  return FDAS_OK;
+}
+
 fdas_status fdas_test_fft(fdas_plan_t pl, int32_t L, int32_t direction, const void* in, void* out, int64_t batch) {
   if (!pl) return FDAS_ERR_ARG;
   if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");

@@ -242,6 +242,93 @@ __global__ __launch_bounds__(256) void k_refine(const void* spec, int64_t nb, do
   }
 }
 
+// Sum over harmonics k = 1..H of a fundamental (r, z): S = sum_k P(k r, k z),
+// dS/dr = sum_k k dP/dr(k r, k z), likewise in z, and the curvature weight
+// sum_k k^2 P_k of the peak model P_k ~ P_k0 (1 - a (k dr)^2 - b (k dz)^2).
+struct HarmEval {
+  double S, gr, gz, curv;
+};
+
+template <int SDT, bool GRAD>
+__device__ inline HarmEval harm_eval(const void* spec, int64_t nb, double r, double z, int H, int margin) {
+  HarmEval h = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 1; k <= H; ++k) {
+    const double kd = (double)k;
+    const RzEval e = rz_eval<SDT, GRAD>(spec, nb, kd * r, kd * z, margin);
+    const double P = e.y.re * e.y.re + e.y.im * e.y.im;
+    h.S += P;
+    if (GRAD) {
+      h.gr += kd * (2.0 * (e.y.re * e.dydr.re + e.y.im * e.dydr.im));
+      h.gz += kd * (2.0 * (e.y.re * e.dydz.re + e.y.im * e.dydz.im));
+      h.curv += kd * kd * P;
+    }
+  }
+  return h;
+}
+
+// Ascent of S at the fundamental with the Newton step of the summed peak
+// model, (dS/dr / (2 a sum k^2 P_k), dS/dz / (2 b sum k^2 P_k)), clamped to
+// 0.25/H bin and 2/H z (a quarter bin at the top harmonic) and halved until S
+// grows.  For H = 1 this is exactly the single-harmonic refinement.
+template <int SDT>
+__global__ __launch_bounds__(256) void k_refine_harm(const void* spec, int64_t nb, double* r, double* z,
+                                                     const int32_t* harm, int64_t n, int iters, int margin,
+                                                     double* p_final) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const int H = harm[c];
+  if (H < 1 || H > 32) {  // invalid count: position untouched, result NaN
+    if ((threadIdx.x & 63) == 0) p_final[c] = __builtin_nan("");
+    return;
+  }
+  constexpr double A = kPi64 * kPi64 / 3.0, B = kPi64 * kPi64 / 180.0;
+  const double hd = (double)H;
+  double rr = r[c], zz = z[c];
+  HarmEval e = harm_eval<SDT, true>(spec, nb, rr, zz, H, margin);
+  for (int it = 0; it < iters && e.S > 0.0; ++it) {
+    double sr = fmin(fmax(e.gr / (2.0 * A * e.curv), -0.25 / hd), 0.25 / hd);
+    double sz = fmin(fmax(e.gz / (2.0 * B * e.curv), -2.0 / hd), 2.0 / hd);
+    bool moved = false;
+    for (int ls = 0; ls < 8; ++ls) {
+      const HarmEval t = harm_eval<SDT, true>(spec, nb, rr + sr, zz + sz, H, margin);
+      if (t.S > e.S) {
+        rr += sr;
+        zz += sz;
+        e = t;
+        moved = true;
+        break;
+      }
+      sr *= 0.5;
+      sz *= 0.5;
+    }
+    if (!moved || (fabs(sr) < 1e-7 / hd && fabs(sz) < 1e-6 / hd)) break;
+  }
+  const HarmEval f = harm_eval<SDT, false>(spec, nb, rr, zz, H, margin);
+  if ((threadIdx.x & 63) == 0) {
+    r[c] = rr;
+    z[c] = zz;
+    p_final[c] = f.S;
+  }
+}
+
+hipError_t launch_refine_harmonics(int sdt, const void* spec, int64_t nb, double* r, double* z, const int32_t* harm,
+                                   int64_t n, int iters, int margin, double* p_final, hipStream_t st) {
+  const dim3 g((unsigned)((n + 3) / 4));
+  switch (sdt) {
+    case FDAS_F32:
+      hipLaunchKernelGGL((k_refine_harm<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, harm, n, iters, margin, p_final);
+      break;
+    case FDAS_BF16:
+      hipLaunchKernelGGL((k_refine_harm<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, harm, n, iters, margin, p_final);
+      break;
+    case FDAS_F16:
+      hipLaunchKernelGGL((k_refine_harm<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, harm, n, iters, margin, p_final);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,
                            double* p, c64* y, hipStream_t st) {
   const dim3 g((unsigned)((n + 3) / 4));

@@ -97,6 +97,8 @@ hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r
                           unsigned long long* acc, hipStream_t st);
 hipError_t launch_refine(int sdt, const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters, int margin,
                          double* p_final, hipStream_t st);
+hipError_t launch_refine_harmonics(int sdt, const void* spec, int64_t nb, double* r, double* z, const int32_t* harm,
+                                   int64_t n, int iters, int margin, double* p_final, hipStream_t st);
 
 // candidate clustering
 int64_t cluster_scratch_bytes(int64_t capacity);

@@ -179,3 +179,104 @@ def test_refine_full_size_sampled(lib):
     tr = np.array([t.r_mean for t in truths])
     tz = np.array([t.z for t in truths])
     assert np.mean((np.abs(rr - tr) < 1.0) & (np.abs(zz - tz) < 1.5)) > 0.99
+
+
+# ------------------------------------------------------- harmonic refinement
+
+def harmonic_trains(seed, n_train, H, n):
+    """Fundamentals drawn in [3000, (N/2 - 400)/H] so that no harmonic of one
+    train comes within 300 bins of a harmonic of another, z in [-20, 20],
+    amplitudes falling as 1/k; each train is H injections (harmonic k at
+    k rbar drifting by k z)."""
+    rng = np.random.default_rng(seed)
+    inj, truth = [], []
+    taken = []
+    for i in range(n_train):
+        while True:
+            rbar = rng.uniform(3000.0, (n // 2 - 400) / H)
+            pos = rbar * np.arange(1, H + 1)
+            if all(np.min(np.abs(pos - p)) > 300 for p in taken):
+                break
+        taken.extend(pos)
+        z = rng.uniform(-20, 20)
+        a0 = rng.uniform(0.04, 0.06)
+        for k in range(1, H + 1):
+            inj.append(synth.Injection(a0 / k, k * (rbar - z / 2), k * z, rng.uniform(0, 2 * np.pi)))
+        truth.append((rbar, z))
+    return inj, np.array(truth)
+
+
+def test_refine_harmonics_with_one_harmonic_is_refine(lib):
+    import torch
+    n = 1 << 18
+    say("fdas_refine_harmonics H = 1 vs fdas_refine", n)
+    pl, spec, a, truths, starts = setup(lib, n, 24, 45)
+    r = torch.tensor(starts[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(starts[:, 1], dtype=torch.float64, device="cuda")
+    r1, z1, p1 = pl.refine(spec, r, z, n_iter=40)
+    r2, z2, p2 = pl.refine_harmonics(spec, r, z, 1, n_iter=40)
+    assert torch.equal(r1, r2) and torch.equal(z1, z2) and torch.equal(p1, p2)
+
+
+def test_refine_harmonics_objective_matches_oracle(lib):
+    """n_iter = 0: S(r, z) for mixed harmonic counts, including positions whose
+    upper harmonics leave the spectrum (zeros there) and invalid counts."""
+    import torch
+    n = 1 << 18
+    say("fdas_refine_harmonics objective", n)
+    inj, truth = harmonic_trains(46, 8, 4, n)
+    x = synth.make_series(n, inj, 46, 0)
+    pl = lib.Plan(n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, make_templates=False)
+    spec = pl.spectrum(torch.from_numpy(x).to("cuda"), [0], [n])
+    a = spec.float().cpu().numpy().astype(np.float64)
+    a = a[:, 0] + 1j * a[:, 1]
+    rng = np.random.default_rng(7)
+    hs = np.array([1, 2, 3, 4, 8, 16, 5, 32] * 4, dtype=np.int32)
+    rr = np.concatenate([truth[:, 0], rng.uniform(100, 20000, 16), [n // 2 / 3 - 1.5, n // 2 / 5 + 0.25,
+                                                                    n // 2 - 10.7, 40.2, 7.9, 60000.5, 1000.0,
+                                                                    2345.6]])
+    zz = np.concatenate([truth[:, 1], rng.uniform(-6, 6, 16), [0.0, 3.0, -5.5, 1e-3, 2.0, -1.0, 0.0, 5.9]])
+    hs = hs[: len(rr)]
+    hs[-2:] = [0, 33]                       # invalid counts
+    r = torch.tensor(rr, dtype=torch.float64, device="cuda")
+    z = torch.tensor(zz, dtype=torch.float64, device="cuda")
+    ro, zo, S = pl.refine_harmonics(spec, r, z, torch.tensor(hs), n_iter=0)
+    S = S.cpu().numpy()
+    assert torch.equal(ro, r) and torch.equal(zo, z)
+    for i in range(len(rr) - 2):
+        want = o.rz_power_harmonics(a, rr[i], zz[i], int(hs[i]))
+        assert abs(S[i] - want) <= 1e-9 * max(1.0, want), (i, hs[i], S[i], want)
+    assert np.isnan(S[-2:]).all()
+
+
+@pytest.mark.parametrize("store,H", [("f32", 4), ("bf16", 4), ("f32", 8)])
+def test_refine_harmonics_reaches_oracle_optimum(lib, store, H):
+    """Harmonic trains in noise, starts off by up to 0.3/H bin and 0.6/H z at
+    the fundamental: the GPU ascent of S reaches the oracle's optimum (S to
+    1e-3; position to 0.02 bin, z to 0.1, or 0.5 where a window step lies in
+    between), and its final S is the oracle's S at the returned position."""
+    import torch
+    n = 1 << 18
+    say("fdas_refine_harmonics", store, H)
+    n_train = 6 if H == 4 else 3
+    inj, truth = harmonic_trains(47 + H, n_train, H, n)
+    x = synth.make_series(n, inj, 47, H)
+    pl = lib.Plan(store=store, n_samples=n, z_min=-96.0, z_max=96.0, z_step=1.0, make_templates=False)
+    spec = pl.spectrum(torch.from_numpy(x).to("cuda"), [0], [n])
+    a = spec.float().cpu().numpy().astype(np.float64)
+    a = a[:, 0] + 1j * a[:, 1]
+    rng = np.random.default_rng(48)
+    st = truth + np.stack([rng.uniform(-0.3, 0.3, n_train), rng.uniform(-0.6, 0.6, n_train)], axis=1) / H
+    r = torch.tensor(st[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(st[:, 1], dtype=torch.float64, device="cuda")
+    rr, zz, S = pl.refine_harmonics(spec, r, z, H, n_iter=60)
+    rr, zz, S = rr.cpu().numpy(), zz.cpu().numpy(), S.cpu().numpy()
+    for i in range(n_train):
+        assert abs(S[i] - o.rz_power_harmonics(a, rr[i], zz[i], H)) <= 1e-9 * S[i]
+        ro, zo, So = o.refine_harmonic_optimum(a, st[i, 0], st[i, 1], H)
+        assert abs(S[i] - So) <= 1e-3 * So, (i, S[i], So)
+        assert abs(rr[i] - ro) <= 0.02, (i, rr[i], ro)
+        same_piece = all(np.ceil(abs(k * zz[i]) / 2) == np.ceil(abs(k * zo) / 2) for k in range(1, H + 1))
+        assert abs(zz[i] - zo) <= (0.1 if same_piece else 0.5), (i, zz[i], zo)
+        # the refined fundamental is the train's, within a bin and 1.5 z at its top harmonic
+        assert abs(rr[i] - truth[i, 0]) * H < 1.0 and abs(zz[i] - truth[i, 1]) * H < 1.5
