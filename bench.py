@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import heapq
 import json
 import math
 import os
@@ -211,29 +212,42 @@ class EnergyMeter:
             pass
 
 
-def energy_leg(torch, meter, runs, bt, seconds=2.0):
+def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=1.0, reps=2):
     """Energy per 10^12 bins x templates of the whole step for each storage
-    type, from the counter over about `seconds` of back-to-back steps, and the
-    idle power over one second before them.  Clocks are whatever the GPU
-    runs at (reported, not set)."""
+    type, from the energy counter over about `seconds` of back-to-back steps.
+    Each window is preceded by `preroll` seconds of the same steps, so that a
+    counter that lags the load still sees only that load inside the window;
+    the storage types alternate `reps` times and the windows are averaged.
+    The idle power is taken over one second after a second of rest.  Clocks
+    are whatever the GPU runs at (reported, not set)."""
     torch.cuda.synchronize()
-    time.sleep(0.5)
+    time.sleep(1.0)
     e0, t0 = meter.joules(), time.perf_counter()
     time.sleep(1.0)
     e1, t1 = meter.joules(), time.perf_counter()
     idle = (e1 - e0) / (t1 - t0)
     out = {"idle_W": idle, "device": meter.matched, "clock_control": "none (default clocks)"}
-    for name, r in runs.items():
-        k = max(20, int(seconds / r["step_s"]))
-        r["step"]()
-        torch.cuda.synchronize()
-        e0, t0 = meter.joules(), time.perf_counter()
-        for _ in range(k):
-            r["step"]()
-        torch.cuda.synchronize()
-        e1, t1 = meter.joules(), time.perf_counter()
-        E, T = e1 - e0, t1 - t0
+    acc = {name: {"E": 0.0, "T": 0.0, "steps": 0, "J_per_1e12_bt_each": [], "ms_per_step_each": []} for name in runs}
+    for _ in range(reps):
+        for name, r in runs.items():
+            for _ in range(max(1, int(preroll / r["step_s"]))):
+                r["step"]()
+            k = max(20, int(seconds / r["step_s"]))
+            e0, t0 = meter.joules(), time.perf_counter()
+            for _ in range(k):
+                r["step"]()
+            torch.cuda.synchronize()
+            e1, t1 = meter.joules(), time.perf_counter()
+            a = acc[name]
+            a["E"] += e1 - e0
+            a["T"] += t1 - t0
+            a["steps"] += k
+            a["J_per_1e12_bt_each"].append((e1 - e0) / (k * bt) * 1e12)
+            a["ms_per_step_each"].append((t1 - t0) / k * 1e3)
+    for name, a in acc.items():
+        E, T, k = a["E"], a["T"], a["steps"]
         out[name] = {"steps": k, "seconds": T, "avg_W": E / T, "J_per_1e12_bt": E / (k * bt) * 1e12,
+                     "J_per_1e12_bt_each": a["J_per_1e12_bt_each"], "ms_per_step_each": a["ms_per_step_each"],
                      "above_idle_J_per_1e12_bt": (E - idle * T) / (k * bt) * 1e12,
                      "avg_gfxclk_MHz": meter.gfxclk_mhz()}
     if "bf16" in out and "f32" in out:
@@ -353,9 +367,21 @@ def refine_leg(torch, fdas, synth):
     tr = np.array([t.r_mean for t in truths])
     tz = np.array([t.z for t in truths])
     rr, zz = rr.cpu().numpy(), zz.cpu().numpy()
+    # the same candidates as fundamentals of 16-harmonic sums (time only: the
+    # series carries single sinusoids); z/16 keeps every harmonic's drift on
+    # the grid's range
+    r16, z16 = r / 16.0, z / 16.0
+    pl.refine_harmonics(spec, r16, z16, 16, n_iter=40)
+    torch.cuda.synchronize()
+    e0.record()
+    pl.refine_harmonics(spec, r16, z16, 16, n_iter=40)
+    e1.record()
+    torch.cuda.synchronize()
+    ms16 = e0.elapsed_time(e1)
     return {"workload": "4096 candidates on one N=2^22 series, 40 ascent iterations", "ms": ms,
             "candidates_per_s": 4096 / (ms / 1e3),
-            "within_1bin_1z_of_truth": float(np.mean((np.abs(rr - tr) < 1.0) & (np.abs(zz - tz) < 1.5)))}
+            "within_1bin_1z_of_truth": float(np.mean((np.abs(rr - tr) < 1.0) & (np.abs(zz - tz) < 1.5))),
+            "harmonics16_ms": ms16, "harmonics16_candidates_per_s": 4096 / (ms16 / 1e3)}
 
 
 def full_leg(args, torch, fdas, synth):
@@ -364,8 +390,10 @@ def full_leg(args, torch, fdas, synth):
     16, 6 sigma, in chunks of up to 16 + 8 + 8 series whose inputs are
     generated on the device before each chunk (untimed).  The search of each
     chunk is timed with HIP events.  Candidates are reduced to local maxima
-    (fdas_cluster, +-2 bins, +-2 trials) and every maximum is refined on its
-    series' spectrum from its cell (R, z_j); the top 1024 by significance are
+    (fdas_cluster, +-2 bins, +-2 trials).  A maximum that can still be among
+    the 1024 most significant so far is refined on its series' spectrum: the
+    sum of its H harmonics, S = sum_k P(k r, k z), is climbed from its grid
+    fundamental (R/H, z_j/H) (fdas_refine_harmonics); the top 1024 are
     reported."""
     N = 1 << 23
     lens_all, truths = synth.ska_full(seed=5, n=N)
@@ -392,6 +420,8 @@ def full_leg(args, torch, fdas, synth):
     search_ms, cluster_ms, refine_ms, n_cands = 0.0, 0.0, 0.0, 0
     found = {}       # trial -> list of (R, z_j) of local maxima
     refined = []     # (sigma, trial, R, zj, r_ref, z_ref, P_cell, P_ref)
+    top_sig = []     # min-heap of the 1024 largest significances so far
+    n_max, n_refined = 0, 0
     for ci, c in enumerate(chunks):
         if ci % 20 == 0:
             print(f"[full run] chunk {ci}/{len(chunks)}", file=sys.stderr, flush=True)
@@ -417,18 +447,32 @@ def full_leg(args, torch, fdas, synth):
         cluster_ms += e0.elapsed_time(e1)
         rec = fdas.candidates_to_numpy(cands, n)
         rec = rec[keep[:n].cpu().numpy().astype(bool)]
+        n_max += len(rec)
+        for s_ in np.unique(rec["series"]):
+            zs_all = -96.0 + rec["j"][rec["series"] == s_].astype(np.float64)
+            found[c[int(s_)]] = list(zip(rec["R"][rec["series"] == s_].tolist(), zs_all.tolist()))
+        # only maxima that can still be in the final top 1024 are refined
+        floor = top_sig[0] if len(top_sig) >= 1024 else -np.inf
+        rec = rec[rec["sigma"] > floor]
+        for v in rec["sigma"].tolist():
+            if len(top_sig) < 1024:
+                heapq.heappush(top_sig, v)
+            elif v > top_sig[0]:
+                heapq.heapreplace(top_sig, v)
+        n_refined += len(rec)
         for s_ in np.unique(rec["series"]):
             m = rec[rec["series"] == s_]
             i = c[int(s_)]
             zj = -96.0 + m["j"].astype(np.float64)
-            found[i] = list(zip(m["R"].tolist(), zj.tolist()))
             nb = lens[int(s_)] // 2
             sp = spec[int(offs[s_]) // 2: int(offs[s_]) // 2 + nb]
-            r0 = torch.tensor(m["R"].astype(np.float64), device="cuda")
-            z0 = torch.tensor(zj, device="cuda")
+            hh = m["harm"].astype(np.float64)
+            r0 = torch.tensor(m["R"].astype(np.float64) / hh, device="cuda")
+            z0 = torch.tensor(zj / hh, device="cuda")
+            hs = torch.tensor(m["harm"].astype(np.int32), device="cuda")
             e0.record()
-            p_cell, _ = pl.rz_power(sp, r0, z0, keep_y=False)
-            rr, zz, pf = pl.refine(sp, r0, z0, n_iter=40)
+            _, _, p_cell = pl.refine_harmonics(sp, r0, z0, hs, n_iter=0)
+            rr, zz, pf = pl.refine_harmonics(sp, r0, z0, hs, n_iter=40)
             e1.record()
             torch.cuda.synchronize()
             refine_ms += e0.elapsed_time(e1)
@@ -451,9 +495,9 @@ def full_leg(args, torch, fdas, synth):
     gain = [pr / pc for _, _, _, _, _, _, pc, pr in top if pc > 0]
     return {"workload": "5925 DM trials (3050 x 2^23, 1500 x 2^22, 1375 x 2^21), 1% with one injection, "
                         f"{len(chunks)} chunks of <= 16+8+8 series, 193 templates, harmonic sums to 16, 6 sigma, "
-                        "local maxima (+-2 bins, +-2 trials) refined, top 1024 reported",
+                        "local maxima (+-2 bins, +-2 trials) refined on their harmonic sums, top 1024 reported",
             "bt_per_s": bt / (search_ms / 1e3), "search_seconds": search_ms / 1e3, "bins_x_templates": bt,
-            "candidates": n_cands, "local_maxima": len(refined), "cluster_seconds": cluster_ms / 1e3,
+            "candidates": n_cands, "local_maxima": n_max, "refined": n_refined, "cluster_seconds": cluster_ms / 1e3,
             "refine_seconds": refine_ms / 1e3,
             "detectable_injections": det, "injections": sum(len(t) for t in truths),
             "recall_detectable": (hit / det) if det else None,

@@ -81,11 +81,47 @@ def test_energy_leg_arithmetic(monkeypatch):
     runs = {"bf16": {"step_s": 1e-3, "step": lambda: advance(1e-3, 600.0)},
             "f32": {"step_s": 2e-3, "step": lambda: advance(2e-3, 500.0)}}
     bt = 8.1e8
-    out = bench.energy_leg(fake_torch(), meter, runs, bt, seconds=0.1)
+    out = bench.energy_leg(fake_torch(), meter, runs, bt, seconds=0.1, preroll=0.05, reps=2)
     assert out["idle_W"] == pytest.approx(100.0)
-    assert out["bf16"]["steps"] == 100 and out["f32"]["steps"] == 50
+    assert out["bf16"]["steps"] == 200 and out["f32"]["steps"] == 100
+    assert len(out["bf16"]["J_per_1e12_bt_each"]) == 2
     assert out["bf16"]["avg_W"] == pytest.approx(600.0)
     assert out["bf16"]["J_per_1e12_bt"] == pytest.approx(0.6 / bt * 1e12)
     assert out["f32"]["J_per_1e12_bt"] == pytest.approx(1.0 / bt * 1e12)
     assert out["f32"]["above_idle_J_per_1e12_bt"] == pytest.approx(0.8 / bt * 1e12)
     assert out["bf16_energy_saving"] == pytest.approx(0.4)
+
+
+def test_energy_leg_is_exact_under_a_lagging_counter(monkeypatch):
+    """A counter that reports the energy of 0.3 s ago: with a pre-roll of at
+    least the lag, every window sees only its own load."""
+    clock = {"t": 0.0}
+    true = {"acc": 0.0}
+    hist = [(0.0, 0.0)]
+    lag = 0.3
+
+    def advance(seconds, watts):
+        clock["t"] += seconds
+        true["acc"] += watts * seconds
+        hist.append((clock["t"], true["acc"]))
+
+    smi = FakeSmi(["0000:75:00.0"], resolution=1.0)
+
+    def lagged(h):
+        t = clock["t"] - lag
+        e = max((a for (ts, a) in hist if ts <= t + 1e-12), default=0.0)
+        return {"energy_accumulator": int(round(e * 1e6)), "counter_resolution": 1.0, "timestamp": 0}
+
+    smi.amdsmi_get_energy_count = lagged
+    meter = bench.EnergyMeter(fake_torch(), smi=smi)
+    monkeypatch.setattr(bench.time, "sleep", lambda s: advance(s, 100.0))
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    runs = {"bf16": {"step_s": 1e-3, "step": lambda: advance(1e-3, 600.0)},
+            "f32": {"step_s": 2e-3, "step": lambda: advance(2e-3, 500.0)}}
+    out = bench.energy_leg(fake_torch(), meter, runs, 1e9, seconds=1.0, preroll=0.5, reps=2)
+    assert out["idle_W"] == pytest.approx(100.0, rel=1e-6)
+    assert out["bf16"]["avg_W"] == pytest.approx(600.0, rel=1e-3)
+    assert out["f32"]["avg_W"] == pytest.approx(500.0, rel=1e-3)
+    # without the pre-roll the first bf16 window would straddle the idle second
+    out0 = bench.energy_leg(fake_torch(), meter, runs, 1e9, seconds=1.0, preroll=0.0, reps=1)
+    assert out0["bf16"]["avg_W"] < 560.0
