@@ -161,6 +161,25 @@ def run_path(fdas, torch, xt, n, args, store, plane, interbin=0):
                 conv_ms=float(np.mean(conv_ms)), harm_ms=float(np.mean(harm_ms)), step=step)
 
 
+def spectrum_norm_timing(torch, fdas, xt, n, store, reps=20):
+    """fdas_spectrum (real FFT + normalisation) of the bench series with the
+    per-block median and with the rednoise sub-blocks, HIP-event timed."""
+    out = {}
+    for norm in ("median", "rednoise"):
+        pl = fdas.Plan(store=store, n_samples=n, norm=norm, make_templates=False)
+        spec = pl.new_spectrum(n // 2)
+        for _ in range(3):
+            pl.spectrum(xt, [0], [n], out=spec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pl.spectrum(xt, [0], [n], out=spec)
+        e1.record()
+        torch.cuda.synchronize()
+        out[norm] = e0.elapsed_time(e1) / reps
+    return out
+
+
 class EnergyMeter:
     """The GPU's energy counter (accumulator x resolution in microjoules) read
     through amdsmi, for the device torch calls cuda:0, matched by PCI address
@@ -677,6 +696,7 @@ def main():
                 meter.close()
         except Exception as e:  # telemetry is optional: report, do not fail the bench
             out["energy"] = {"error": f"{type(e).__name__}: {e}"}
+    out["spectrum_ms_by_norm"] = spectrum_norm_timing(torch, fdas, xt, n, args.store)
     if not args.no_interbin:
         rib = run_path(fdas, torch, xt, n, args, args.store, plane_dt, interbin=1)
         out["interbin"] = {

@@ -65,7 +65,7 @@ typedef enum {
 
 typedef enum { FDAS_F32 = 0, FDAS_BF16 = 1, FDAS_F16 = 2 } fdas_dtype;
 
-typedef enum { FDAS_NORM_NONE = 0, FDAS_NORM_VARIANCE = 1, FDAS_NORM_MEDIAN = 2 } fdas_norm;
+typedef enum { FDAS_NORM_NONE = 0, FDAS_NORM_VARIANCE = 1, FDAS_NORM_MEDIAN = 2, FDAS_NORM_REDNOISE = 3 } fdas_norm;
 
 typedef struct {
   int64_t n_samples;         /* N of the longest series: a power of two, 2^17 .. 2^23 */
@@ -150,7 +150,11 @@ fdas_status fdas_make_templates(fdas_plan_t plan);
 /* Spectrum: real FFT of every series, A_r = sum_n x_n exp(-2 pi i r n/N) for
  * r < N/2 (Nyquist dropped, A_0 set to 0), then normalisation: NONE; VARIANCE
  * A/sqrt(N sigma^2); MEDIAN A sqrt(ln2/m_b) with m_b the lower median of |A|^2
- * (rank (B-1)/2) in each block of B bins (a zero median scales the block by 0).
+ * (rank (B-1)/2) in each block of B bins (a zero median scales the block by 0);
+ * REDNOISE as MEDIAN, but block b (bins b B ... (b+1) B - 1) is cut into equal
+ * sub-blocks of width w_b = clamp(largest power of two <= b B / 8, 32, B), each
+ * scaled by its own lower median (whitening of a steep low-frequency
+ * continuum: a block is at most an eighth of its frequency wide).
  * spectrum_out: store_dtype complex, packed as described above. */
 fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out);

@@ -84,6 +84,13 @@ def normalise(a: np.ndarray, mode: str, block: int = 2048, noise_var: float = 1.
       bins; m_b is the lower median of |A|^2 in the block; A' = A sqrt(ln2/m_b).
       The median of an Exp(1) variable is ln 2, so noise powers become Exp(1).
       A block whose median is zero is scaled by zero.
+    * ``rednoise`` (READING: whitening of a red-noise continuum ahead of the
+      search, which the paper leaves implicit): as ``median``, but the block
+      of B bins starting at bin s = b B is cut into equal sub-blocks of
+      width rednoise_width(b, B) = clamp(largest power of two <= s/8, 32, B),
+      each scaled by its own lower median.  A block is then at most an
+      eighth of its frequency wide, so a power law f^-2 varies by at most
+      (9/8)^2 across it; from bin 8 B on the blocks are whole.
     """
     a = np.asarray(a, dtype=np.complex128)
     if mode == "none":
@@ -92,13 +99,32 @@ def normalise(a: np.ndarray, mode: str, block: int = 2048, noise_var: float = 1.
         n = n_samples if n_samples is not None else 2 * a.shape[-1]
         out = a / math.sqrt(n * noise_var)
         return (out, None) if return_medians else out
-    if mode != "median":
+    if mode not in ("median", "rednoise"):
         raise ValueError(mode)
     p = a.real ** 2 + a.imag ** 2
-    med = block_lower_median(p, block)
-    scale = np.where(med > 0, np.sqrt(LN2 / np.where(med > 0, med, 1.0)), 0.0)
-    out = (a.reshape(-1, block) * scale[:, None]).reshape(a.shape)
-    return (out, med) if return_medians else out
+    if mode == "median":
+        med = block_lower_median(p, block)
+        scale = np.where(med > 0, np.sqrt(LN2 / np.where(med > 0, med, 1.0)), 0.0)
+        out = (a.reshape(-1, block) * scale[:, None]).reshape(a.shape)
+        return (out, med) if return_medians else out
+    out = np.empty_like(a)
+    meds = []
+    for b in range(a.shape[-1] // block):
+        w = rednoise_width(b, block)
+        seg = slice(b * block, (b + 1) * block)
+        med = block_lower_median(p[seg], w)
+        scale = np.where(med > 0, np.sqrt(LN2 / np.where(med > 0, med, 1.0)), 0.0)
+        out[seg] = (a[seg].reshape(-1, w) * scale[:, None]).reshape(-1)
+        meds.append(med)
+    return (out, meds) if return_medians else out
+
+
+def rednoise_width(b: int, block: int) -> int:
+    """Sub-block width inside block b of the rednoise normalisation: the
+    largest power of two <= b*block/8, kept within [32, block]."""
+    s8 = b * block // 8
+    w = 1 << (s8.bit_length() - 1) if s8 > 0 else 1
+    return int(min(max(w, 32), block))
 
 
 # ------------------------------------------------------------------- z grid

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "libfdas.so")
 
 F32, BF16, F16 = 0, 1, 2
 DTYPES = {"f32": F32, "bf16": BF16, "f16": F16}
-NORMS = {"none": 0, "variance": 1, "median": 2}
+NORMS = {"none": 0, "variance": 1, "median": 2, "rednoise": 3}
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED",
           5: "ERR_OVERFLOW", 6: "ERR_NONFINITE", 7: "ERR_STATE"}

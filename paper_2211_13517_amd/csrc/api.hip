@@ -160,7 +160,7 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   if (4 * hmax > L) return bad("segment_len must be at least 4 * h_max (h_max = ceil(z_max/2) + margin)");
   for (int dt : {p.store_dtype, p.plane_dtype})
     if (dt < FDAS_F32 || dt > FDAS_F16) return bad("store_dtype / plane_dtype must be FDAS_F32, FDAS_BF16 or FDAS_F16");
-  if (p.norm < FDAS_NORM_NONE || p.norm > FDAS_NORM_MEDIAN) return bad("unknown norm");
+  if (p.norm < FDAS_NORM_NONE || p.norm > FDAS_NORM_REDNOISE) return bad("unknown norm");
   const int B = p.norm_block ? p.norm_block : 2048;
   if (!is_pow2(B) || B < 256 || B > 4096) return bad("norm_block must be a power of two in [256, 4096]");
   if (p.norm == FDAS_NORM_VARIANCE && !(p.noise_var > 0)) return bad("noise_var must be > 0");

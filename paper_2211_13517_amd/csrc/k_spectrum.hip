@@ -172,6 +172,14 @@ __device__ uint32_t block_select(const uint32_t* keys, int n, int k, int* hist, 
   return prefix;
 }
 
+// Sub-block width of the rednoise normalisation in block b of B bins: the
+// largest power of two <= b B / 8, kept within [32, B].
+__device__ __forceinline__ int rednoise_width(int b, int B) {
+  const int s8 = (b * B) >> 3;
+  const int w = s8 > 0 ? 1 << (31 - __clz(s8)) : 1;
+  return min(max(w, 32), B);
+}
+
 template <int SDT>
 __global__ __launch_bounds__(256) void k_unpack_norm(const SeriesDesc* __restrict__ desc,
                                                      const int32_t* __restrict__ list, int M, int B, int mode,
@@ -184,6 +192,7 @@ __global__ __launch_bounds__(256) void k_unpack_norm(const SeriesDesc* __restric
   __shared__ int hist[256];
   __shared__ int wsum[4];
   __shared__ int sel[2];
+  __shared__ float subscale[128];  // rednoise: one scale per sub-block (B / 32 <= 128)
   const SeriesDesc d = desc[list[blockIdx.y]];
   const c32* zb = Zb + d.spec_off;
   const int N = 2 * M;
@@ -204,17 +213,45 @@ __global__ __launch_bounds__(256) void k_unpack_norm(const SeriesDesc* __restric
     keys[i] = __float_as_uint(p);
   }
   const int bad = __syncthreads_or(mybad);
+  constexpr float kLn2 = 0.69314718055994530942f;
   float scale = var_scale;
-  if (mode == FDAS_NORM_MEDIAN) {
+  const int w = mode == FDAS_NORM_REDNOISE ? rednoise_width(blockIdx.x, B) : B;
+  if (mode == FDAS_NORM_MEDIAN || (mode == FDAS_NORM_REDNOISE && w == B)) {
     const uint32_t m = block_select(keys, B, (B - 1) / 2, hist, wsum, sel);
     const float med = __uint_as_float(m);
-    scale = med > 0.f ? sqrtf(0.69314718055994530942f / med) : 0.f;
+    scale = med > 0.f ? sqrtf(kLn2 / med) : 0.f;
+  } else if (mode == FDAS_NORM_REDNOISE) {
+    if (w <= 256) {
+      // small sub-blocks: each element's rank within its sub-block by direct
+      // count (ties ordered by position); rank (w-1)/2 is the lower median
+      for (int i = threadIdx.x; i < B; i += 256) {
+        const int base = i & ~(w - 1);
+        const uint32_t ki = keys[i];
+        int rank = 0;
+        for (int l = 0; l < w; ++l) {
+          const uint32_t kl = keys[base + l];
+          rank += (kl < ki) || (kl == ki && base + l < i);
+        }
+        if (rank == (w - 1) / 2) {
+          const float med = __uint_as_float(ki);
+          subscale[i / w] = med > 0.f ? sqrtf(kLn2 / med) : 0.f;
+        }
+      }
+    } else {
+      for (int j = 0; j < B / w; ++j) {
+        const float med = __uint_as_float(block_select(keys + j * w, w, (w - 1) / 2, hist, wsum, sel));
+        if (threadIdx.x == 0) subscale[j] = med > 0.f ? sqrtf(kLn2 / med) : 0.f;
+      }
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0 && bad) atomicOr(status, 1);
   typename SS::cplx_t* out = reinterpret_cast<typename SS::cplx_t*>(spec) + d.spec_off + (size_t)blockIdx.x * B;
+  const bool sub = mode == FDAS_NORM_REDNOISE && w < B;
   for (int i = threadIdx.x; i < B; i += 256) {
     const c32 v = a[i];
-    out[i] = SS::pack(c32{v.re * scale, v.im * scale});
+    const float sc = sub ? subscale[i / w] : scale;
+    out[i] = SS::pack(c32{v.re * sc, v.im * sc});
   }
 }
 

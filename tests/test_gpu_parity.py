@@ -80,7 +80,7 @@ def test_spectrum_matches_oracle(lib, n):
     say("fdas_spectrum", n)
     x = synth.make_series(n, [synth.Injection(0.05, 5000.0, 12.0, 0.3)], 21, n)
     xt = torch.from_numpy(x).to("cuda")
-    for norm in ("none", "median", "variance"):
+    for norm in ("none", "median", "variance", "rednoise"):
         plan = lib.Plan(n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, segment_len=1024, norm=norm,
                         make_templates=False)
         s = to_np_complex(plan.spectrum(xt, [0], [n]))
@@ -109,6 +109,39 @@ def test_median_block_selection_is_exact(lib):
     got_scale = np.abs(b[:, 0] + 1j * b[:, 1]).reshape(-1, 2048)[:, 5:] / np.abs(
         a[:, 0].astype(np.float64) + 1j * a[:, 1]).reshape(-1, 2048)[:, 5:]
     np.testing.assert_allclose(np.median(got_scale, axis=1), scale, rtol=2e-6)
+
+
+@pytest.mark.parametrize("B", [256, 2048, 4096])
+def test_rednoise_sub_block_selection_is_exact(lib, B):
+    """Rednoise normalisation: in every sub-block (width 32 ... B by the
+    frequency rule) the GPU's scale is sqrt(ln2 / m) of the exact rank-(w-1)/2
+    element of the FP32 powers, on a series with a steep red continuum."""
+    import torch
+    n = 1 << 18
+    say("fdas_spectrum rednoise exact", n, B)
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(n) + 24.0 * np.cumsum(rng.standard_normal(n)) / math.sqrt(n)
+    x = (x - x.mean()).astype(np.float32)
+    xt = torch.from_numpy(x).to("cuda")
+    kw = dict(n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, norm_block=B, make_templates=False)
+    raw = lib.Plan(norm="none", **kw)
+    red = lib.Plan(norm="rednoise", **kw)
+    a = raw.spectrum(xt, [0], [n]).cpu().numpy().astype(np.float32)
+    b = red.spectrum(xt, [0], [n]).cpu().numpy().astype(np.float64)
+    p32 = a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1]
+    mag_a = np.abs(a[:, 0].astype(np.float64) + 1j * a[:, 1])
+    mag_b = np.abs(b[:, 0] + 1j * b[:, 1])
+    checked = 0
+    for blk in range(min(n // 2 // B, 12)):
+        w = o.rednoise_width(blk, B)
+        for j in range(B // w):
+            lo = blk * B + j * w
+            m = np.sort(p32[lo: lo + w])[(w - 1) // 2].astype(np.float64)
+            ok = mag_a[lo: lo + w] > 0
+            got = np.median(mag_b[lo: lo + w][ok] / mag_a[lo: lo + w][ok])
+            assert abs(got / math.sqrt(math.log(2.0) / m) - 1) < 2e-6, (blk, j, w)
+            checked += 1
+    assert checked >= 12
 
 
 # ---------------------------------------------------------------- power plane

@@ -77,6 +77,55 @@ def test_median_normalisation_constructed_blocks():
         assert abs(np.sort(np.abs(seg) ** 2)[(b - 1) // 2] - math.log(2)) < 1e-14
 
 
+def test_rednoise_widths_follow_the_rule():
+    # sub-block width: largest power of two <= (block start)/8, within [32, B]
+    assert [o.rednoise_width(b, 2048) for b in range(10)] == [32, 256, 512, 512, 1024, 1024, 1024, 1024, 2048, 2048]
+    assert [o.rednoise_width(b, 256) for b in range(9)] == [32, 32, 64, 64, 128, 128, 128, 128, 256]
+
+
+def test_rednoise_normalisation_constructed_sub_blocks():
+    # every sub-block of width w holds a permutation of {1..w} times its own
+    # factor, so its lower median is (w // 2) times that factor exactly
+    B, nblk = 256, 10
+    rng = np.random.default_rng(3)
+    parts, want = [], []
+    f = 1.0
+    for b in range(nblk):
+        w = o.rednoise_width(b, B)
+        for _ in range(B // w):
+            f *= 1.37
+            vals = rng.permutation(np.arange(1, w + 1, dtype=np.float64)) * f
+            parts.append(np.sqrt(vals) * np.exp(1j * rng.uniform(0, 2 * np.pi, w)))
+            want.append((w, (w // 2) * f))
+    a = np.concatenate(parts)
+    out, meds = o.normalise(a, "rednoise", block=B, return_medians=True)
+    np.testing.assert_allclose(np.concatenate(meds), [m for _, m in want], rtol=1e-15)
+    pos = 0
+    for w, m in want:
+        np.testing.assert_allclose(out[pos:pos + w], a[pos:pos + w] * math.sqrt(math.log(2) / m), rtol=1e-15)
+        pos += w
+
+
+def test_rednoise_normalisation_whitens_a_steep_continuum():
+    # white noise plus a random walk (power ~ 1/f^2, 1e4 times the white level
+    # at bin 100): per-block medians leave the lowest bins far from unit mean,
+    # frequency-scaled sub-blocks bring them back within the median's scatter
+    n = 1 << 18
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(n) + 0.6 * np.cumsum(rng.standard_normal(n)) / math.sqrt(n) * 40
+    x = (x - x.mean()).astype(np.float32)
+    a = o.spectrum(x)
+    for mode, bound in (("rednoise", 0.25), ("median", None)):
+        p = np.abs(o.normalise(a, mode)) ** 2
+        means = [p[lo:lo + 64].mean() for lo in range(64, 2048, 64)]
+        if bound is None:
+            assert max(means) > 5.0       # the block median cannot follow the slope
+        else:
+            assert max(abs(np.log(means))) < math.log(1 + 4 * bound), means
+    p = np.abs(o.normalise(a, "rednoise")) ** 2
+    assert abs(p[16384:].mean() - 1.0) < 0.01   # whole blocks higher up
+
+
 def test_median_normalisation_noise_unit_mean():
     x = synth.make_series(1 << 20, [], cfg_seed=9, series_index=0)
     a = o.normalise(o.spectrum(x), "median")
