@@ -251,6 +251,7 @@ def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=1.0, reps=2):
         for name, r in runs.items():
             for _ in range(max(1, int(preroll / r["step_s"]))):
                 r["step"]()
+            torch.cuda.synchronize()  # the window must not inherit queued pre-roll work
             k = max(20, int(seconds / r["step_s"]))
             e0, t0 = meter.joules(), time.perf_counter()
             for _ in range(k):
