@@ -231,7 +231,7 @@ class EnergyMeter:
             pass
 
 
-def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=1.0, reps=2):
+def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=2):
     """Energy per 10^12 bins x templates of the whole step for each storage
     type, from the energy counter over about `seconds` of back-to-back steps.
     Each window is preceded by `preroll` seconds of the same steps, so that a
