@@ -9,9 +9,11 @@ sinusoids, already resident in HBM.  Throughput is bins x templates per second
 in bfloat16 (FP32 arithmetic); the FP32-storage path is timed beside it.
 
 Prints one JSON line.  Extra legs: the FP64 oracle timed on a bounded sample
-of the same workload on the host (cpu_baseline), the power error of both paths
-against the oracle at detections, the recall of the injections, and the
-refinement of 4096 off-grid candidates on a 2^22-bin spectrum.
+of the same workload on the host (cpu_baseline, the only use of the oracle
+here), the power error of the BF16 path against the FP32 path at detections,
+the recall of the injections, the energy per unit of work, the same step on a
+half-bin plane, and the refinement of 4096 off-grid candidates on a 2^22-bin
+spectrum.
 
 Kernel durations come from HIP events recorded on the plan's stream around
 each stage of every timed step.  The roofline object describes the kernel
@@ -47,7 +49,7 @@ def parse():
     ap.add_argument("--plane", default=None, help="plane dtype (default: same as --store)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage comparison leg")
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle error/recall leg")
+    ap.add_argument("--no-check", action="store_true", help="skip the power error / recall leg")
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement leg")
     ap.add_argument("--no-interbin", action="store_true", help="skip the half-bin plane leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-counter leg")
@@ -303,15 +305,13 @@ def midway_recall(torch, fdas, synth, runs, n, n_inj=64, p0=44.0):
     return out
 
 
-def oracle_checks(o, synth, x, inj, res, Z):
-    """Relative power error at detections (sampled) and injection recall."""
-    zs = o.z_grid(-96, 96, 1)
-    taps, _ = o.template_taps(zs)
-    a = o.normalise(o.spectrum(x), "median")
-    nb = len(x) // 2
-    P = res["plane"].view(Z, nb)
-    # detections: every cell within +-3 bins and +-4 z of each injection's peak,
-    # plus cells above tau_1 found by the GPU (sampled)
+def precision_checks(res, ref, inj, Z, tau1):
+    """Relative power error of a reduced-precision plane at detections, against
+    the FP32-storage plane of the same series on the same GPU (the parity
+    tests hold that plane to 1e-4 of the FP64 oracle): every cell within
+    +-3 bins and +-4 z of each injection's peak whose FP32 power is at least
+    tau_1.  Plus the recall of the injections by each path's candidates."""
+    nb = res["plane"].numel() // Z
     rows, cols = [], []
     for i in inj:
         rc, jc = int(round(i.r_mean)), int(round(i.z + 96))
@@ -320,18 +320,20 @@ def oracle_checks(o, synth, x, inj, res, Z):
                 if 0 <= jc + dj < Z:
                     rows.append(jc + dj)
                     cols.append(rc + dr)
-    rows, cols = np.array(rows), np.array(cols)
-    ref = o.power_cells(a, taps, rows, cols)
-    got = P[torch_index(rows), torch_index(cols)].float().cpu().numpy().astype(np.float64)
-    det = ref >= o.threshold(1)
-    rel = np.abs(got - ref) / ref
-    c = fdas_cands(res)
-    found = 0
-    for i in inj:
-        ok = np.any((np.abs(c["r"] - i.r_mean) <= 1.0) & (np.abs(c["z"] - i.z) <= 1.0)) if len(c) else False
-        found += bool(ok)
-    return dict(n_det=int(det.sum()), max_rel=float(rel[det].max()), median_rel=float(np.median(rel[det])),
-                recall=found / len(inj))
+    ri, ci = torch_index(rows), torch_index(cols)
+    got = res["plane"].view(Z, nb)[ri, ci].float().cpu().numpy().astype(np.float64)
+    want = ref["plane"].view(Z, nb)[ri, ci].float().cpu().numpy().astype(np.float64)
+    det = want >= tau1
+    rel = np.abs(got - want) / want
+
+    def recall(r):
+        c = fdas_cands(r)
+        return sum(bool(np.any((np.abs(c["r"] - i.r_mean) <= 1.0) & (np.abs(c["z"] - i.z) <= 1.0))) if len(c) else False
+                   for i in inj) / len(inj)
+
+    return dict(reference="FP32-storage plane of the same series", n_det=int(det.sum()),
+                max_rel=float(rel[det].max()), median_rel=float(np.median(rel[det])),
+                recall=recall(res), recall_reference=recall(ref))
 
 
 _torch = None
@@ -683,11 +685,9 @@ def main():
                        "harmonic_sum_ms": r32["harm_ms"]}
         out["speedup_vs_fp32"] = {"step": r32["step_s"] / res["step_s"], "conv": r32["conv_ms"] / res["conv_ms"],
                                   "harmonic_sum": r32["harm_ms"] / res["harm_ms"]}
-    if not args.no_check:
-        from oracle import fdas64 as o
-        out["accuracy"] = {args.store: oracle_checks(o, synth, x, inj, res, Z)}
-        if not args.no_fp32:
-            out["accuracy"]["f32"] = oracle_checks(o, synth, x, inj, r32, Z)
+    if not args.no_check and not args.no_fp32 and args.store != "f32":
+        tau1 = float(res["plan"].thresholds()[0])
+        out["accuracy"] = {args.store: precision_checks(res, r32, inj, Z, tau1)}
     if not args.no_energy and not args.no_fp32 and args.store == "bf16":
         try:
             meter = EnergyMeter(torch)
