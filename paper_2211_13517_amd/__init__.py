@@ -365,7 +365,8 @@ def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) ->
         else:
             setattr(p, k, v)
     name = torch.cuda.get_device_properties(device).gcnArchName if torch.cuda.is_available() else "none"
-    key = f"{name}|N={p.n_samples}|z={p.z_min},{p.z_max},{p.z_step}|m={p.kernel_margin}|s={p.store_dtype}|p={p.plane_dtype}"
+    key = (f"{name}|N={p.n_samples}|z={p.z_min},{p.z_max},{p.z_step}|m={p.kernel_margin}|s={p.store_dtype}"
+           f"|p={p.plane_dtype}|ib={p.interbin}")
     cache = cache or os.environ.get("FDAS_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fdas_tune.json"))
     table = {}
     if os.path.exists(cache):

@@ -207,3 +207,46 @@ def test_interbin_ska_full_size_sampled(lib):
     assert np.all(c["R"] < 2 * (n // 2 - pl.hmax))
     k = keep[: len(c)].cpu().numpy().astype(bool)
     assert np.array_equal(k, o.local_maxima(c["series"], c["R"], c["j"], c["sigma"], 2, 2))
+
+
+def test_interbin_argument_errors_enqueue_nothing(lib):
+    """Host-side checks of the half-bin path: a plane buffer sized for the bin
+    plane, or misaligned for (bin, half-bin) pairs, is refused before any
+    launch and leaves the buffer untouched."""
+    import ctypes
+    import torch
+    n = 1 << 17
+    say("interbin argument errors", n)
+    pl = lib.Plan(store="f32", plane="f32", n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, segment_len=1024,
+                  interbin=1)
+    spec = pl.spectrum(torch.from_numpy(synth.make_series(n, [], 3, 0)).to("cuda"), [0], [n])
+    small = torch.full((pl.Z * n // 2,), -1.0, device="cuda")            # bin-plane size: too small
+    with pytest.raises(lib.FdasError, match="too small"):
+        pl.convolve_spectrum(spec, [n], plane=small)
+    big = torch.full((pl.Z * n + 1,), -1.0, device="cuda")
+    lens = (ctypes.c_int64 * 1)(n)
+    st = pl.lib.fdas_convolve_spectrum(pl.handle, ctypes.c_void_p(spec.data_ptr()), lens, 1,
+                                       ctypes.c_void_p(big.data_ptr() + 4), (pl.Z * n) * 4)
+    assert st == 1 and b"aligned" in pl.lib.fdas_last_error(pl.handle)
+    torch.cuda.synchronize()
+    assert bool((small == -1.0).all()) and bool((big == -1.0).all())
+
+
+def test_refine_harmonics_argument_errors(lib):
+    import ctypes
+    import torch
+    n = 1 << 17
+    say("fdas_refine_harmonics argument errors", n)
+    pl = lib.Plan(n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, make_templates=False)
+    spec = pl.spectrum(torch.from_numpy(synth.make_series(n, [], 4, 0)).to("cuda"), [0], [n])
+    r = torch.tensor([1000.0], dtype=torch.float64, device="cuda")
+    z = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = torch.zeros(1, dtype=torch.float64, device="cuda")
+    f = pl.lib.fdas_refine_harmonics
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert f(pl.handle, vp(spec), n // 2, vp(r), vp(z), None, 1, 10, vp(p)) == 1          # no counts
+    assert f(pl.handle, vp(spec), n // 2, vp(r), vp(z), vp(r), 1, -1, vp(p)) == 1         # n_iter < 0
+    assert f(pl.handle, vp(spec), n, vp(r), vp(z), vp(r), 1, 10, vp(p)) == 1              # n_bins too large
+    assert f(pl.handle, vp(spec), n // 2, vp(r), vp(z), None, 0, 10, vp(p)) == 0          # nothing to do
+    with pytest.raises(ValueError):
+        pl.refine_harmonics(spec, r, z, torch.tensor([1, 2]))

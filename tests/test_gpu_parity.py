@@ -534,18 +534,20 @@ def test_search_graph_replays_match_eager(lib):
         assert len(want) > 0
 
 
-def test_autotune_picks_a_valid_configuration(lib):
+@pytest.mark.parametrize("interbin", [0, 1])
+def test_autotune_picks_a_valid_configuration(lib, interbin):
     import torch
     n = 1 << 18
-    say("fdas_autotune", n)
+    say("fdas_autotune", n, interbin)
     best = lib.autotune(cache="/tmp/fdas_tune_test.json", n_samples=n, z_min=-32.0, z_max=32.0, z_step=1.0,
-                        store="bf16", plane="bf16")
+                        store="bf16", plane="bf16", interbin=interbin)
+    assert best.interbin == interbin
     assert best.segment_len in (1024, 2048, 4096, 8192)
     x = synth.make_series(n, [synth.Injection(0.05, 7000.0, 21.0, 0.3)], 52, 0)
     pl = lib.Plan(params=best, n_samples=n)
     P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
     zs = o.z_grid(-32, 32, 1)
     ref = o.power_plane(o.normalise(o.spectrum(x), "median"), zs, rows=[0, 25, 32, 53, 64])
-    got = P.view(pl.Z, n // 2).float().cpu().numpy()[[0, 25, 32, 53, 64]]
+    got = P.view(pl.Z, n // 2 * pl.res).float().cpu().numpy()[[0, 25, 32, 53, 64]][:, ::pl.res]
     e = o.power_errors(got, ref, tau1=o.threshold(1))
     assert e["max_rel_det"] < 3e-2
