@@ -285,8 +285,9 @@ fdas_status fdas_copy_thresholds(fdas_plan_t plan, double *tau_host);
  * as those calls leave them); d_count: device int64 record count; keep:
  * device uint8 [capacity]; scratch: caller-owned device memory of at least
  * fdas_cluster_scratch_bytes(capacity) bytes, 8-byte aligned, overwritten.
- * Radii in [0, 64].  Enqueued on the plan's stream; allocates nothing.
- * fdas_cluster_scratch_bytes returns -1 for a negative capacity. */
+ * Radii in [0, 64], capacity at most 2^30.  Enqueued on the plan's stream;
+ * allocates nothing.  fdas_cluster_scratch_bytes returns -1 for a capacity
+ * outside [0, 2^30]. */
 int64_t fdas_cluster_scratch_bytes(int64_t capacity);
 fdas_status fdas_cluster(fdas_plan_t plan, const fdas_candidate *cands, const int64_t *d_count, int64_t capacity,
                          int32_t radius_r, int32_t radius_j, void *scratch, int64_t scratch_bytes, uint8_t *keep);

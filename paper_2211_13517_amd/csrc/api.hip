@@ -721,7 +721,9 @@ fdas_status fdas_copy_templates(fdas_plan_t pl, void* taps_out, void* spectra_ou
   return FDAS_OK;
 }
 
-int64_t fdas_cluster_scratch_bytes(int64_t capacity) { return capacity < 0 ? -1 : cluster_scratch_bytes(capacity); }
+int64_t fdas_cluster_scratch_bytes(int64_t capacity) {
+  return capacity < 0 || capacity > (int64_t(1) << 30) ? -1 : cluster_scratch_bytes(capacity);
+}
 
 fdas_status fdas_cluster(fdas_plan_t pl, const fdas_candidate* cands, const int64_t* d_count, int64_t capacity,
                          int32_t radius_r, int32_t radius_j, void* scratch, int64_t scratch_bytes, uint8_t* keep) {
@@ -730,6 +732,7 @@ fdas_status fdas_cluster(fdas_plan_t pl, const fdas_candidate* cands, const int6
     return pl->fail(FDAS_ERR_ARG, "d_count is required; cands and keep when capacity > 0");
   if (radius_r < 0 || radius_r > 64 || radius_j < 0 || radius_j > 64)
     return pl->fail(FDAS_ERR_ARG, "radius_r and radius_j must be in [0, 64]");
+  if (capacity > (int64_t(1) << 30)) return pl->fail(FDAS_ERR_ARG, "capacity must be at most 2^30 records");
   if (capacity == 0) return FDAS_OK;
   if (!scratch || scratch_bytes < cluster_scratch_bytes(capacity) || (((uintptr_t)scratch) & 7))
     return pl->fail(FDAS_ERR_NOMEM, "scratch missing, misaligned or smaller than fdas_cluster_scratch_bytes(capacity)");

@@ -104,3 +104,6 @@ def test_cluster_scratch_size_is_host_only(lib):
     # a power-of-two table of at least twice the records, 12 bytes a slot
     assert L.fdas_cluster_scratch_bytes(1000) == 2048 * 12
     assert L.fdas_cluster_scratch_bytes(1 << 20) == (1 << 21) * 12
+    # record indices are 32-bit and the table at most 2^31 slots
+    assert L.fdas_cluster_scratch_bytes(1 << 30) == (1 << 31) * 12
+    assert L.fdas_cluster_scratch_bytes((1 << 30) + 1) == -1
