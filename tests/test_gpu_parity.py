@@ -245,6 +245,50 @@ def test_plane_ska_full_size_sampled(lib, L, store, plane):
     assert np.all(g[-len(inj):] > o.threshold(1))
 
 
+@pytest.mark.parametrize("store,tol", [("bf16", 3e-2), ("f32", 1e-4)])
+def test_power_error_and_recall_against_oracle_ska_single(lib, store, tol):
+    """The precision statement at full size, in the bench's configuration
+    (N = 2^23, 193 templates, L = 1024, 8 injections): relative power error
+    against the FP64 oracle at every cell within +-3 bins and +-4 z of each
+    injection's peak whose oracle power is at least tau_1, and recall of the
+    injections by the GPU's harmonic-sum candidates (within 1 bin and 1 z)."""
+    import torch
+    x, inj, params = synth.ska_single(seed=2)
+    params = dict(params)
+    params["segment_len"] = 1024
+    params.pop("norm")
+    say("precision vs oracle, SKA single", store)
+    pl, P, _ = gpu_plane(lib, x, params, store=store, plane=store)
+    n = len(x)
+    nb = n // 2
+    zs = o.z_grid(-96, 96, 1)
+    taps, _ = o.template_taps(zs)
+    a = o.normalise(o.spectrum(x), "median")
+    rows, cols = [], []
+    for i in inj:
+        rc, jc = int(round(i.r_mean)), int(round(i.z + 96))
+        for dj in range(-4, 5):
+            for dr in range(-3, 4):
+                if 0 <= jc + dj < pl.Z:
+                    rows.append(jc + dj)
+                    cols.append(rc + dr)
+    rows, cols = np.array(rows), np.array(cols)
+    ref = o.power_cells(a, taps, rows, cols)
+    got = P.view(pl.Z, nb)[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].float().cpu().numpy()
+    det = ref >= o.threshold(1)
+    rel = np.abs(got.astype(np.float64) - ref)[det] / ref[det]
+    cap = 1 << 20
+    cands, count = pl.harmonic_sum(P, [n], capacity=cap)
+    pl.check(count, cap)
+    c = lib.candidates_to_numpy(cands, int(count.item()))
+    found = sum(bool(np.any((np.abs(c["r"] - i.r_mean) <= 1.0) & (np.abs(c["z"] - i.z) <= 1.0))) for i in inj)
+    say(f"{store}: {det.sum()} detection cells, max rel {rel.max():.3e}, median rel {np.median(rel):.3e}, "
+        f"recall {found}/{len(inj)}")
+    assert det.sum() >= 100
+    assert rel.max() < tol
+    assert found == len(inj)
+
+
 # ---------------------------------------------------------------- harmonic sum
 
 def run_search(lib, x, params, store="f32", plane="f32", capacity=1 << 16):
