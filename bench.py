@@ -530,7 +530,8 @@ def full_leg(args, torch, fdas, synth):
 def batch_leg(args, torch, fdas, synth):
     """Batching: 512 uneven DM trials, chunks of 16 x 2^23 + 8 x 2^22 + 8 x 2^21
     series (one HIP graph, replayed per chunk after the chunk's series are
-    copied into the working buffer); BF16 storage, harmonic sums to 16, 6 sigma."""
+    copied into the working buffer); BF16 storage, segment length and template
+    grouping from the autotuner, harmonic sums to 16, 6 sigma."""
     N = 1 << 23
     per_chunk = [N] * 16 + [N // 2] * 8 + [N // 4] * 8
     n_chunks = 16
@@ -550,12 +551,16 @@ def batch_leg(args, torch, fdas, synth):
         for s_, i in enumerate(idx[c]):
             o0 = c * chunk_samples + int(offs[s_])
             synth.fill_series_device(allx[o0: o0 + per_chunk[s_]], truths[i], 3, i)
+    # segment length and templates per tile from the autotuner (a full-length
+    # series timed for every allowed L and template grouping on this GPU)
+    tuned = fdas.autotune(cache=os.path.join("/tmp", "fdas_tune_bench.json"), n_samples=N, z_min=-96.0,
+                          z_max=96.0, z_step=1.0, store=args.store, plane=args.plane or args.store)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         pl = fdas.Plan(store=args.store, plane=args.plane or args.store, n_samples=N, max_batch_samples=chunk_samples,
-                       z_min=-96.0, z_max=96.0, z_step=1.0, n_harmonics=16, segment_len=args.segment_len,
-                       stream=stream)
+                       z_min=-96.0, z_max=96.0, z_step=1.0, n_harmonics=16, segment_len=tuned.segment_len,
+                       templates_per_tile=tuned.templates_per_tile, stream=stream)
         work = torch.empty(chunk_samples, dtype=torch.float32, device="cuda")
         plane = pl.new_plane(chunk_samples // 2)
         cap = 1 << 23  # strong injections leave ~10^5 passing cells each
@@ -597,6 +602,7 @@ def batch_leg(args, torch, fdas, synth):
     return {"workload": "512 uneven DM trials (256 x 2^23, 128 x 2^22, 128 x 2^21), 16 graph replays of "
                         "32-series chunks, 193 templates, harmonic sums to 16, 6 sigma",
             "bt_per_s": bt / dt, "seconds": dt, "bins_x_templates": bt, "segment_len": pl.L,
+            "templates_per_tile": int(tuned.templates_per_tile), "autotuned": True,
             "recall_detectable": (hit / det) if det else None, "detectable_injections": det,
             "injections": sum(len(t) for t in truths)}
 
