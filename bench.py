@@ -704,6 +704,14 @@ def main():
         except Exception as e:  # telemetry is optional: report, do not fail the bench
             out["energy"] = {"error": f"{type(e).__name__}: {e}"}
     out["spectrum_ms_by_norm"] = spectrum_norm_timing(torch, fdas, xt, n, args.store)
+    if L != 8192:
+        # the segment length the SKA-like configuration names, for comparison
+        a8 = argparse.Namespace(**vars(args))
+        a8.segment_len = 8192
+        r8 = run_path(fdas, torch, xt, n, a8, args.store, plane_dt)
+        out["segment_8192"] = {"value": bt / r8["step_s"], "ms_per_step": r8["step_s"] * 1e3,
+                               "conv_ms": r8["conv_ms"], "harmonic_sum_ms": r8["harm_ms"]}
+        del r8
     if not args.no_interbin:
         rib = run_path(fdas, torch, xt, n, args, args.store, plane_dt, interbin=1)
         out["interbin"] = {
