@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement leg")
     ap.add_argument("--no-interbin", action="store_true", help="skip the half-bin plane leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-counter leg")
+    ap.add_argument("--only-step", action="store_true",
+                    help="the timed step and the FP32 comparison only (no other leg): for profiler runs")
     ap.add_argument("--n", type=int, default=1 << 23)
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 1 GiB device copy (for counters)")
     ap.add_argument("--json-out", default=None)
@@ -610,6 +612,8 @@ def batch_leg(args, torch, fdas, synth):
 def main():
     global _torch
     args = parse()
+    if args.only_step:
+        args.no_cpu_baseline = args.no_check = args.no_refine = args.no_interbin = args.no_energy = True
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over "
                                    "GPUs is designed but not built)"}))
@@ -703,8 +707,9 @@ def main():
                 meter.close()
         except Exception as e:  # telemetry is optional: report, do not fail the bench
             out["energy"] = {"error": f"{type(e).__name__}: {e}"}
-    out["spectrum_ms_by_norm"] = spectrum_norm_timing(torch, fdas, xt, n, args.store)
-    if L != 8192:
+    if not args.only_step:
+        out["spectrum_ms_by_norm"] = spectrum_norm_timing(torch, fdas, xt, n, args.store)
+    if L != 8192 and not args.only_step:
         # the segment length the SKA-like configuration names, for comparison
         a8 = argparse.Namespace(**vars(args))
         a8.segment_len = 8192
