@@ -151,7 +151,8 @@ fdas_status fdas_make_templates(fdas_plan_t plan);
  * r < N/2 (Nyquist dropped, A_0 set to 0), then normalisation: NONE; VARIANCE
  * A/sqrt(N sigma^2); MEDIAN A sqrt(ln2/m_b) with m_b the lower median of |A|^2
  * (rank (B-1)/2) in each block of B bins (a zero median scales the block by 0);
- * REDNOISE as MEDIAN, but block b (bins b B ... (b+1) B - 1) is cut into equal
+ * REDNOISE (an addition for red-noise continua, which the paper leaves
+ * implicit) as MEDIAN, but block b (bins b B ... (b+1) B - 1) is cut into equal
  * sub-blocks of width w_b = clamp(largest power of two <= b B / 8, 32, B), each
  * scaled by its own lower median (whitening of a steep low-frequency
  * continuum: a block is at most an eighth of its frequency wide).
@@ -223,10 +224,11 @@ fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n
 fdas_status fdas_refine(fdas_plan_t plan, const void *spectrum, int64_t n_bins, double *r, double *z, int64_t n,
                         int32_t n_iter, double *p_final);
 
-/* Harmonic refinement: the same ascent on the incoherent harmonic power of a
- * fundamental (r, z) (harmonic k of a signal drifting by z bins lies at k r and
- * drifts by k z; a candidate of stage H is refined on the sum it was found
- * with):
+/* Harmonic refinement (an addition: the paper stops at candidates; this
+ * refines a harmonic-sum candidate of the introduction's harmonic summing on
+ * the sum it was found with): the same ascent on the incoherent harmonic
+ * power of a fundamental (r, z), harmonic k of a signal drifting by z bins
+ * lying at k r and drifting by k z:
  *   S(r, z) = sum_{k=1}^{H} P(k r, k z),  dS/dr = sum_k k dP/dr(k r, k z), likewise z,
  * step (dS/dr / (2 a W), dS/dz / (2 b W)) with W = sum_k k^2 P(k r, k z),
  * clamped to 0.25/H bin and 2/H z and halved until S grows; for H = 1 exactly
@@ -275,9 +277,10 @@ fdas_status fdas_copy_templates(fdas_plan_t plan, void *taps_out, void *spectra_
  * array tau_host (log2(n_harmonics)+1 values). */
 fdas_status fdas_copy_thresholds(fdas_plan_t plan, double *tau_host);
 
-/* Candidate clustering (local maxima), the first step of sifting the records
- * of fdas_harmonic_sum / fdas_search: a strong signal leaves a patch of
- * passing cells around its peak.  Record i (i < min(*d_count, capacity)) gets
+/* Candidate clustering (local maxima; an addition: the paper stops at
+ * candidates), the first step of sifting the records of fdas_harmonic_sum /
+ * fdas_search: a strong signal leaves a patch of passing cells around its
+ * peak.  Record i (i < min(*d_count, capacity)) gets
  * keep[i] = 1 when no record of the same series with |R' - R| <= radius_r and
  * |j' - j| <= radius_j has a larger sigma (equal sigma: the record with the
  * smaller (j, R) wins), else 0 (R in the records' units: half bins after a
