@@ -83,15 +83,11 @@ template <> struct PowerPair<FDAS_F32> {
 };
 template <> struct PowerPair<FDAS_BF16> {
   typedef uint32_t type;
-  __device__ __forceinline__ static type pack(float p, float h) {
-    return (uint32_t)Store<FDAS_BF16>::pack_real(p) | ((uint32_t)Store<FDAS_BF16>::pack_real(h) << 16);
-  }
+  __device__ __forceinline__ static type pack(float p, float h) { return Store<FDAS_BF16>::pack(c32{p, h}); }
 };
 template <> struct PowerPair<FDAS_F16> {
   typedef uint32_t type;
-  __device__ __forceinline__ static type pack(float p, float h) {
-    return (uint32_t)Store<FDAS_F16>::pack_real(p) | ((uint32_t)Store<FDAS_F16>::pack_real(h) << 16);
-  }
+  __device__ __forceinline__ static type pack(float p, float h) { return Store<FDAS_F16>::pack(c32{p, h}); }
 };
 
 template <class FS, int SDT, int PDT, bool BLOCK, bool IB>
