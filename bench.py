@@ -235,12 +235,13 @@ class EnergyMeter:
             pass
 
 
-def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=2):
+def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=3):
     """Energy per 10^12 bins x templates of the whole step for each storage
     type, from the energy counter over about `seconds` of back-to-back steps.
     Each window is preceded by `preroll` seconds of the same steps, so that a
     counter that lags the load still sees only that load inside the window;
-    the storage types alternate `reps` times and the windows are averaged.
+    the storage types alternate `reps` times and the median window is
+    reported (a window whose counter reading glitches does not move it).
     The idle power is taken over one second after a second of rest.  Clocks
     are whatever the GPU runs at (reported, not set)."""
     torch.cuda.synchronize()
@@ -250,7 +251,8 @@ def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=2):
     e1, t1 = meter.joules(), time.perf_counter()
     idle = (e1 - e0) / (t1 - t0)
     out = {"idle_W": idle, "device": meter.matched, "clock_control": "none (default clocks)"}
-    acc = {name: {"E": 0.0, "T": 0.0, "steps": 0, "J_per_1e12_bt_each": [], "ms_per_step_each": []} for name in runs}
+    acc = {name: {"E": 0.0, "T": 0.0, "steps": 0, "J_per_1e12_bt_each": [], "ms_per_step_each": [], "W_each": []}
+           for name in runs}
     for _ in range(reps):
         for name, r in runs.items():
             for _ in range(max(1, int(preroll / r["step_s"]))):
@@ -268,11 +270,14 @@ def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=2):
             a["steps"] += k
             a["J_per_1e12_bt_each"].append((e1 - e0) / (k * bt) * 1e12)
             a["ms_per_step_each"].append((t1 - t0) / k * 1e3)
+            a["W_each"].append((e1 - e0) / (t1 - t0))
     for name, a in acc.items():
-        E, T, k = a["E"], a["T"], a["steps"]
-        out[name] = {"steps": k, "seconds": T, "avg_W": E / T, "J_per_1e12_bt": E / (k * bt) * 1e12,
+        j = float(np.median(a["J_per_1e12_bt_each"]))
+        w = float(np.median(a["W_each"]))
+        ms = float(np.median(a["ms_per_step_each"]))
+        out[name] = {"steps": a["steps"], "seconds": a["T"], "avg_W": w, "J_per_1e12_bt": j,
                      "J_per_1e12_bt_each": a["J_per_1e12_bt_each"], "ms_per_step_each": a["ms_per_step_each"],
-                     "above_idle_J_per_1e12_bt": (E - idle * T) / (k * bt) * 1e12,
+                     "above_idle_J_per_1e12_bt": j - idle * ms * 1e-3 / bt * 1e12,
                      "avg_gfxclk_MHz": meter.gfxclk_mhz()}
     if "bf16" in out and "f32" in out:
         out["bf16_energy_saving"] = 1.0 - out["bf16"]["J_per_1e12_bt"] / out["f32"]["J_per_1e12_bt"]

@@ -125,3 +125,37 @@ def test_energy_leg_is_exact_under_a_lagging_counter(monkeypatch):
     # without the pre-roll the first bf16 window would straddle the idle second
     out0 = bench.energy_leg(fake_torch(), meter, runs, 1e9, seconds=1.0, preroll=0.0, reps=1)
     assert out0["bf16"]["avg_W"] < 560.0
+
+
+def test_energy_leg_median_ignores_one_glitched_window(monkeypatch):
+    """One window whose counter reading comes back halved does not move the
+    reported energy: the median of three windows is taken."""
+    clock = {"t": 0.0}
+    smi = FakeSmi(["0000:75:00.0"], resolution=1.0)
+    reads = {"n": 0}
+    real = smi.amdsmi_get_energy_count
+
+    def glitchy(h):
+        reads["n"] += 1
+        e = real(h)
+        # the closing read of the second bf16 window (reads: 2 idle, then 2 per window, bf16 first)
+        if reads["n"] == 2 + 2 * 2 + 2:
+            e = dict(e, energy_accumulator=e["energy_accumulator"] - 300_000_000)   # half a window
+        return e
+
+    smi.amdsmi_get_energy_count = glitchy
+    meter = bench.EnergyMeter(fake_torch(), smi=smi)
+
+    def advance(seconds, watts):
+        clock["t"] += seconds
+        smi.acc[0] += int(round(watts * seconds * 1e6))
+
+    monkeypatch.setattr(bench.time, "sleep", lambda s: advance(s, 100.0))
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    runs = {"bf16": {"step_s": 1e-3, "step": lambda: advance(1e-3, 600.0)},
+            "f32": {"step_s": 2e-3, "step": lambda: advance(2e-3, 500.0)}}
+    out = bench.energy_leg(fake_torch(), meter, runs, 1e9, seconds=1.0, preroll=0.1, reps=3)
+    each = out["bf16"]["J_per_1e12_bt_each"]
+    assert min(each) < 0.9 * max(each)                         # the glitch is visible
+    assert out["bf16"]["avg_W"] == pytest.approx(600.0, rel=1e-3)
+    assert out["bf16"]["J_per_1e12_bt"] == pytest.approx(0.6 * 1e-3 / 1e9 * 1e12 * 1000, rel=1e-3)
