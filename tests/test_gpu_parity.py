@@ -527,6 +527,24 @@ def test_candidate_overflow_is_reported(lib):
     assert count.item() > 3
 
 
+def test_counting_only_and_empty_batch(lib):
+    """capacity = 0 counts the passing cells without storing any, the same
+    count as with room for all of them; a batch of no series is refused."""
+    import ctypes
+    import torch
+    n = 1 << 17
+    x = synth.make_series(n, [synth.Injection(0.06, 3000.0, 8.0, 0.1)], 10, 0)
+    say("fdas_harmonic_sum capacity 0")
+    pl, P, _ = gpu_plane(lib, x, small_params(1024))
+    _, full = pl.harmonic_sum(P, [n], capacity=1 << 16)
+    _, none = pl.harmonic_sum(P, [n], capacity=0)
+    pl.check(full, 1 << 16)
+    assert int(none.item()) == int(full.item()) > 0
+    lens = (ctypes.c_int64 * 1)(n)
+    assert pl.lib.fdas_harmonic_sum(pl.handle, ctypes.c_void_p(P.data_ptr()), lens, 0, None, 0,
+                                    ctypes.c_void_p(full.data_ptr())) == 1
+
+
 def test_nonfinite_input_is_reported(lib):
     import torch
     n = 1 << 17
