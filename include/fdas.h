@@ -199,6 +199,8 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
  *   P = |y|^2, evaluated in FP64.
  * spectrum: store_dtype complex [n_bins] (one series, e.g. from fdas_spectrum);
  * r, z, p: double [n] device arrays (positions need FP64: bins reach 2^22);
+ * a position that is not finite, has |z| > 2^17 or |r| >= 2^52 gives NaN (in
+ * every output of these calls, and fdas_refine* leave it where it is);
  * y_out (optional, complex128 [n]) keeps y for the adjoint.
  * n_bins <= max_batch_samples / 2. */
 fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r, const double *z,

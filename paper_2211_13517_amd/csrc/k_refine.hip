@@ -117,9 +117,20 @@ struct RzEval {
   c64 y, dydr, dydz;
 };
 
+// Positions the evaluation accepts: finite, |r| < 2^52 (so floor(r) is exact
+// in int64) and |z| <= 2^17 (a window of at most 2^17 + 2 margin bins).
+// Anything else evaluates to NaN without touching the spectrum, so that no
+// input can make the window loop run away.
+constexpr double kMaxAbsZ = 131072.0, kMaxAbsR = 4503599627370496.0;
+__device__ inline bool rz_valid(double r, double z) { return fabs(r) < kMaxAbsR && fabs(z) <= kMaxAbsZ; }
+
 // One wavefront evaluates y (and optionally its r, z derivatives) at (r, z).
 template <int SDT, bool GRAD>
 __device__ inline RzEval rz_eval(const void* spec, int64_t nb, double r, double z, int margin) {
+  if (!rz_valid(r, z)) {  // also false for NaN
+    const double q = __builtin_nan("");
+    return RzEval{{q, q}, {q, q}, {q, q}};
+  }
   const int64_t k0 = (int64_t)floor(r);
   const int w = margin + (int)ceil(fabs(z) * 0.5);
   const int lane = threadIdx.x & 63;
@@ -174,7 +185,7 @@ __global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, c
     gr[c] = g * 2.0 * (y.re * e.dydr.re + y.im * e.dydr.im);
     gz[c] = g * 2.0 * (y.re * e.dydz.re + y.im * e.dydz.im);
   }
-  if (!acc) return;
+  if (!acc || !rz_valid(rr, zz)) return;
   // dP/dA_k = 2 y rho(k - r, z), accumulated in 2^-40 fixed point: integer
   // addition is associative, so the sum does not depend on arrival order.
   const int64_t k0 = (int64_t)floor(rr);

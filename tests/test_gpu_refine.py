@@ -280,3 +280,28 @@ def test_refine_harmonics_reaches_oracle_optimum(lib, store, H):
         assert abs(zz[i] - zo) <= (0.1 if same_piece else 0.5), (i, zz[i], zo)
         # the refined fundamental is the train's, within a bin and 1.5 z at its top harmonic
         assert abs(rr[i] - truth[i, 0]) * H < 1.0 and abs(zz[i] - truth[i, 1]) * H < 1.5
+
+
+def test_invalid_positions_give_nan(lib):
+    """Non-finite r or z, |z| > 2^17 or |r| >= 2^52 evaluate to NaN without
+    touching the spectrum; refinement leaves such candidates where they are
+    (the values used here are harmless even without the check: a NaN window
+    converts to zero width, z just past 2^17 to a finite window, and r = 2^53
+    reads only bins past the spectrum)."""
+    import torch
+    n = 1 << 17
+    say("invalid refinement positions", n)
+    pl = lib.Plan(n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, make_templates=False)
+    spec = pl.spectrum(torch.from_numpy(synth.make_series(n, [], 5, 0)).to("cuda"), [0], [n])
+    r = torch.tensor([float("nan"), 1000.0, 2.0 ** 53, 1000.3], dtype=torch.float64, device="cuda")
+    z = torch.tensor([0.0, 131074.0, 0.0, 2.0], dtype=torch.float64, device="cuda")
+    p, y = pl.rz_power(spec, r, z)
+    p = p.cpu().numpy()
+    assert np.isnan(p[:3]).all() and np.isfinite(p[3])
+    gr, gz, gs = pl.rz_power_grad(spec, r, z, torch.ones(4, dtype=torch.float64, device="cuda"))
+    assert np.isnan(gr.cpu().numpy()[:3]).all() and torch.isfinite(gs).all()
+    rr, zz, pf = pl.refine(spec, r, z, n_iter=5)
+    assert torch.equal(zz[:3], z[:3]) and torch.equal(rr[1:3], r[1:3]) and np.isnan(pf.cpu().numpy()[:3]).all()
+    r2, z2, S = pl.refine_harmonics(spec, torch.tensor([500.0], dtype=torch.float64, device="cuda"),
+                                    torch.tensor([70000.0], dtype=torch.float64, device="cuda"), 16, n_iter=3)
+    assert np.isnan(S.cpu().numpy()).all()   # harmonic 2 already lies at z = 140000
