@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement leg")
     ap.add_argument("--no-interbin", action="store_true", help="skip the half-bin plane leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-counter leg")
+    ap.add_argument("--interbin", action="store_true",
+                    help="time the step on the half-bin plane (implies --only-step --no-fp32)")
     ap.add_argument("--only-step", action="store_true",
                     help="the timed step and the FP32 comparison only (no other leg): for profiler runs")
     ap.add_argument("--n", type=int, default=1 << 23)
@@ -89,17 +91,19 @@ def measured_traffic(kernel: str, key: str):
     return t.get("per_launch_bytes", {}).get(key)
 
 
-def algorithmic(L, U, hmax, Z, nbins, store_bytes, plane_bytes):
+def algorithmic(L, U, hmax, Z, nbins, store_bytes, plane_bytes, interbin=False):
     """Per launch of the convolve->power kernel: bytes and flops the method needs.
 
     Bytes: the spectrum read once, the template spectra read once, the plane
-    written once.  Flops (FFT convention 5 L log2 L per complex FFT): one forward
-    FFT per segment, and per segment and template a complex product (6 L), an
-    inverse FFT and |y|^2 of the U useful outputs (3 U)."""
+    written once (plane_bytes per bin: both columns on a half-bin plane).
+    Flops (FFT convention 5 L log2 L per complex FFT): one forward FFT per
+    segment, and per segment and template a complex product (6 L), an inverse
+    FFT and |y|^2 of the U useful outputs (3 U), plus the half-bin power
+    |y_i - y_{i+1}|^2 / 2 (6 U) on a half-bin plane."""
     nseg = math.ceil(nbins / U)
     bytes_ = nbins * store_bytes + Z * L * store_bytes + Z * nbins * plane_bytes
     fft = 5.0 * L * math.log2(L)
-    flops = nseg * fft + nseg * Z * (6.0 * L + fft + 3.0 * U)
+    flops = nseg * fft + nseg * Z * (6.0 * L + fft + (9.0 if interbin else 3.0) * U)
     return bytes_, flops
 
 
@@ -617,6 +621,8 @@ def batch_leg(args, torch, fdas, synth):
 def main():
     global _torch
     args = parse()
+    if args.interbin:
+        args.only_step = args.no_fp32 = True
     if args.only_step:
         args.no_cpu_baseline = args.no_check = args.no_refine = args.no_interbin = args.no_energy = True
     if args.gpus != 1:
@@ -639,18 +645,18 @@ def main():
     x, inj, _ = synth.ska_single(seed=2, n=n)
     xt = torch.from_numpy(x).to("cuda")
     plane_dt = args.plane or args.store
-    res = run_path(fdas, torch, xt, n, args, args.store, plane_dt)
+    res = run_path(fdas, torch, xt, n, args, args.store, plane_dt, interbin=1 if args.interbin else 0)
     pl = res["plan"]
     Z, L, U, hmax = pl.Z, pl.L, pl.U, pl.hmax
     nb = n // 2
     bt = nb * Z
     sb = 8 if args.store == "f32" else 4
-    pb = 4 if plane_dt == "f32" else 2
-    abytes, aflops = algorithmic(L, U, hmax, Z, nb, sb, pb)
+    pb = (4 if plane_dt == "f32" else 2) * pl.res   # plane bytes per bin (two columns on a half-bin plane)
+    abytes, aflops = algorithmic(L, U, hmax, Z, nb, sb, pb, interbin=args.interbin)
     conv_s = res["conv_ms"] / 1e3
     harm_s = res["harm_ms"] / 1e3
     hbytes = harm_bytes(Z, nb, pb)
-    key = f"{args.store}/{plane_dt}/{L}/{n}"
+    key = f"{args.store}/{plane_dt}/{L}/{n}" + ("/interbin" if args.interbin else "")
     out = {
         "metric": "bins*templates/s for FDAS conv, BF16 vs FP32 at <=3% power err; HBM GB/s",
         "value": bt / res["step_s"],
@@ -666,7 +672,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"SKA-like single series: N=2^{int(math.log2(n))} float32, 8 injected accelerated "
                                f"sinusoids, 193 templates z in [-96,96] step 1, segment {L}, median normalisation, "
-                               f"harmonic sums to 16, 6 sigma",
+                               f"harmonic sums to 16, 6 sigma" + (", half-bin plane" if args.interbin else ""),
                    "storage": args.store, "plane": plane_dt, "segment_len": L, "templates": Z, "bins": nb},
     }
     # Both big kernels against their rooflines.  convolve->power is bound by
