@@ -277,6 +277,80 @@ __device__ inline HarmEval harm_eval(const void* spec, int64_t nb, double r, dou
   return h;
 }
 
+// The same sums with four harmonics evaluated at once: the wavefront splits
+// into four groups of 16 lanes, group g taking harmonics g + 1, g + 5, ...;
+// each group reduces its harmonic over its 16 lanes, then the four groups'
+// partial sums are added.  Short windows (32-40 bins at small z) keep all
+// 64 lanes busy this way instead of about half of them.
+template <int SDT, bool GRAD>
+__device__ inline HarmEval harm_eval4(const void* spec, int64_t nb, double r, double z, int H, int margin) {
+  constexpr int GL = 16;
+  const int lane = threadIdx.x & 63, g = lane / GL, gl = lane % GL;
+  HarmEval h = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 1; k0 <= H; k0 += 64 / GL) {
+    const int k = k0 + g;
+    const double kd = (double)k, kr = kd * r, kz = kd * z;
+    c64 y = {0.0, 0.0}, dr = {0.0, 0.0}, dz = {0.0, 0.0};
+    if (k <= H && rz_valid(kr, kz)) {
+      const int64_t b0 = (int64_t)floor(kr);
+      const int w = margin + (int)ceil(fabs(kz) * 0.5);
+      for (int t = gl; t < 2 * w; t += GL) {
+        const int64_t b = b0 - w + 1 + t;
+        const c64 a = spec_at<SDT>(spec, nb, b);
+        if (a.re == 0.0 && a.im == 0.0) continue;
+        if (GRAD) {
+          const RhoD d = response_d64((double)b - kr, kz);
+          y = c64add(y, c64mul(a, c64conj(d.rho)));
+          dr = c64sub(dr, c64mul(a, c64conj(d.dq)));
+          dz = c64add(dz, c64mul(a, c64conj(d.dz)));
+        } else {
+          y = c64add(y, c64mul(a, c64conj(response64((double)b - kr, kz))));
+        }
+      }
+    } else if (k <= H) {
+      y.re = __builtin_nan("");  // an invalid harmonic makes S NaN
+    }
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) {
+      y.re += __shfl_xor(y.re, o, 64);
+      y.im += __shfl_xor(y.im, o, 64);
+      if (GRAD) {
+        dr.re += __shfl_xor(dr.re, o, 64);
+        dr.im += __shfl_xor(dr.im, o, 64);
+        dz.re += __shfl_xor(dz.re, o, 64);
+        dz.im += __shfl_xor(dz.im, o, 64);
+      }
+    }
+    if (k <= H) {
+      const double P = y.re * y.re + y.im * y.im;
+      h.S += P;
+      if (GRAD) {
+        h.gr += kd * (2.0 * (y.re * dr.re + y.im * dr.im));
+        h.gz += kd * (2.0 * (y.re * dz.re + y.im * dz.im));
+        h.curv += kd * kd * P;
+      }
+    }
+  }
+  // every lane of a group holds its group's sums: add the four groups
+#pragma unroll
+  for (int o = GL; o < 64; o <<= 1) {
+    h.S += __shfl_xor(h.S, o, 64);
+    if (GRAD) {
+      h.gr += __shfl_xor(h.gr, o, 64);
+      h.gz += __shfl_xor(h.gz, o, 64);
+      h.curv += __shfl_xor(h.curv, o, 64);
+    }
+  }
+  return h;
+}
+
+// One harmonic: the single-harmonic evaluation itself (so that H = 1 is
+// fdas_refine step for step); more: four at a time.
+template <int SDT, bool GRAD>
+__device__ inline HarmEval harm_sum(const void* spec, int64_t nb, double r, double z, int H, int margin) {
+  return H == 1 ? harm_eval<SDT, GRAD>(spec, nb, r, z, H, margin) : harm_eval4<SDT, GRAD>(spec, nb, r, z, H, margin);
+}
+
 // Ascent of S at the fundamental with the Newton step of the summed peak
 // model, (dS/dr / (2 a sum k^2 P_k), dS/dz / (2 b sum k^2 P_k)), clamped to
 // 0.25/H bin and 2/H z (a quarter bin at the top harmonic) and halved until S
@@ -295,13 +369,13 @@ __global__ __launch_bounds__(256) void k_refine_harm(const void* spec, int64_t n
   constexpr double A = kPi64 * kPi64 / 3.0, B = kPi64 * kPi64 / 180.0;
   const double hd = (double)H;
   double rr = r[c], zz = z[c];
-  HarmEval e = harm_eval<SDT, true>(spec, nb, rr, zz, H, margin);
+  HarmEval e = harm_sum<SDT, true>(spec, nb, rr, zz, H, margin);
   for (int it = 0; it < iters && e.S > 0.0; ++it) {
     double sr = fmin(fmax(e.gr / (2.0 * A * e.curv), -0.25 / hd), 0.25 / hd);
     double sz = fmin(fmax(e.gz / (2.0 * B * e.curv), -2.0 / hd), 2.0 / hd);
     bool moved = false;
     for (int ls = 0; ls < 8; ++ls) {
-      const HarmEval t = harm_eval<SDT, true>(spec, nb, rr + sr, zz + sz, H, margin);
+      const HarmEval t = harm_sum<SDT, true>(spec, nb, rr + sr, zz + sz, H, margin);
       if (t.S > e.S) {
         rr += sr;
         zz += sz;
@@ -314,7 +388,7 @@ __global__ __launch_bounds__(256) void k_refine_harm(const void* spec, int64_t n
     }
     if (!moved || (fabs(sr) < 1e-7 / hd && fabs(sz) < 1e-6 / hd)) break;
   }
-  const HarmEval f = harm_eval<SDT, false>(spec, nb, rr, zz, H, margin);
+  const HarmEval f = harm_sum<SDT, false>(spec, nb, rr, zz, H, margin);
   if ((threadIdx.x & 63) == 0) {
     r[c] = rr;
     z[c] = zz;
