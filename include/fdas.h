@@ -119,7 +119,11 @@ typedef struct {
  * N = 2^23, tsamp 64 us).  Never fails for a non-NULL p. */
 fdas_status fdas_default_params(fdas_params *p);
 
-/* Validates *params and creates a plan bound to `device` and the HIP stream
+/* Plan (section 2.1: the search is set by the series length and sampling,
+ * the acceleration trials z = fdot T^2 and the harmonics summed; section 3:
+ * the SKA-like workload, 2^23 samples at 64 us, the longest series a plan
+ * takes, searched over 193 acceleration trials).
+ * Validates *params and creates a plan bound to `device` and the HIP stream
  * `hip_stream` (NULL = default stream).  Derived sizes: Z = (z_max - z_min)/z_step + 1,
  * h_max = ceil(z_max/2) + m, U = L - 2 h_max outputs per segment (one fewer on
  * a half-bin plane).  Thresholds
@@ -160,7 +164,10 @@ fdas_status fdas_make_templates(fdas_plan_t plan);
 fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out);
 
-/* Convolution from a normalised spectrum (store_dtype, packed): overlap-save
+/* Convolution (section 2.2: the correlation with every template runs in the
+ * frequency domain through FFTs, this stage's data stored in store_dtype and
+ * its arithmetic in FP32; section 2.1: one output row per acceleration trial).
+ * From a normalised spectrum (store_dtype, packed): overlap-save
  * segments of L bins starting at s U - h_max (zero outside [0, N/2)), one
  * forward FFT per segment, then for every template j: product with T_j,
  * inverse FFT, and P[j][s U + i] = |y[h_max + i]|^2 for i < U, i.e.
@@ -171,13 +178,17 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
 fdas_status fdas_convolve_spectrum(fdas_plan_t plan, const void *spectrum, const int64_t *lengths_host,
                                    int32_t n_series, void *plane_out, int64_t plane_bytes);
 
-/* Spectrum and convolution in one call: fdas_spectrum then fdas_convolve_spectrum.
+/* Spectrum and convolution in one call (sections 2.1 and 2.2, as the two
+ * entry points it chains): fdas_spectrum then fdas_convolve_spectrum.
  * spectrum_out may be NULL, in which case the spectrum lives in the workspace. */
 fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out,
                           void *plane_out, int64_t plane_bytes);
 
-/* Harmonic sums: nested harmonic sums and thresholding over a packed plane.
+/* Harmonic sums (the introduction's harmonic-summing stage, which follows the
+ * correlation; the paper names it without formulas, so the index rule below
+ * is this library's reading): nested harmonic sums and thresholding over a
+ * packed plane.  plane: device, 16-byte aligned (FDAS_ERR_ARG otherwise).
  * For cell (R, j) with m = j - j0 (j0 the z = 0 trial) and H the top stage,
  *   S_H(R, j) = sum_{k=1}^{H} P[j0 + sgn(m) floor((2k|m| + H)/(2H))][floor((2kR + H)/(2H))],
  * and the lower stages H' use the terms k = H/H', 2H/H', ..., H.  A cell is
@@ -192,8 +203,10 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);
 
-/* Off-grid power, forward: Fourier-interpolated matched-filter power at off-grid
- * candidates (section 2.1's matched filter evaluated between grid points):
+/* Off-grid power, forward (an addition: the paper stops at grid candidates;
+ * this is section 2.1's matched filter evaluated between grid points, the
+ * differentiable form used for refinement): Fourier-interpolated
+ * matched-filter power at off-grid candidates:
  *   y(r, z) = sum_{k = k0-w+1}^{k0+w} A_k conj(rho(k - r, z)),  k0 = floor(r),
  *   w = kernel_margin + ceil(|z|/2) (32 bins at z = 0), A_k = 0 outside [0, n_bins),
  *   P = |y|^2, evaluated in FP64.
@@ -206,7 +219,8 @@ fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t
 fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r, const double *z,
                           int64_t n, double *p, void *y_out);
 
-/* Off-grid power, adjoint: given the upstream gradient grad_p[i] of a real loss with
+/* Off-grid power, adjoint (an addition, like fdas_rz_power): given the
+ * upstream gradient grad_p[i] of a real loss with
  * respect to p[i], writes grad_r[i] = grad_p 2 Re(conj(y) dy/dr),
  * grad_z[i] = grad_p 2 Re(conj(y) dy/dz) (dy/dr = -sum A_k conj(d rho/dq),
  * dy/dz = sum A_k conj(d rho/dz), FP64), and, if grad_spectrum is non-NULL,
@@ -218,7 +232,9 @@ fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n
                                const double *z, const void *y, const double *grad_p, int64_t n, double *grad_r,
                                double *grad_z, void *grad_spectrum);
 
-/* Refinement: n_iter steps of preconditioned gradient ascent of
+/* Refinement (an addition: the paper stops at grid candidates; this climbs
+ * the off-grid power of fdas_rz_power from a candidate): n_iter steps of
+ * preconditioned gradient ascent of
  * P(r, z) per candidate (step (dP/dr / (2 a P), dP/dz / (2 b P)) with
  * a = pi^2/3, b = pi^2/180, clamped to 0.25 bin and 2 z, halved until P
  * grows), r and z updated in place (double [n]), and the final power evaluated

@@ -105,6 +105,8 @@ struct fdas_plan_s {
   }
 };
 
+// Release calls on cleanup paths ((void) below) drop their status on purpose:
+// a failed release leaves nothing for the caller to undo.
 static fdas_status hip_fail(fdas_plan_t pl, hipError_t e, const char* what) {
   return pl->fail(FDAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -196,8 +198,11 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   for (int i = 0; i < pl->nstages; ++i) pl->tau[i] = threshold_for(1 << i, sig);
   pl->max_batch = mb;
   pl->max_series = (int)(mb / (p.n_samples / 4));
-  hipDeviceGetAttribute(&pl->cu_count, hipDeviceAttributeMultiprocessorCount, device);
-  if (pl->cu_count <= 0) pl->cu_count = 256;
+  if (hipDeviceGetAttribute(&pl->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      pl->cu_count <= 0) {
+    delete pl;
+    return bad("could not query the device's compute-unit count");
+  }
 
   // workspace layout
   int64_t o = 0;
@@ -227,7 +232,7 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
 
   if (hipHostMalloc((void**)&pl->h_desc_pinned, sizeof(SeriesDesc) * pl->max_series) != hipSuccess ||
       hipHostMalloc((void**)&pl->h_lists_pinned, sizeof(int32_t) * pl->max_series) != hipSuccess) {
-    if (pl->h_desc_pinned) hipHostFree(pl->h_desc_pinned);
+    if (pl->h_desc_pinned) (void)hipHostFree(pl->h_desc_pinned);
     delete pl;
     return bad("could not allocate pinned host staging");
   }
@@ -250,6 +255,13 @@ fdas_status fdas_set_workspace(fdas_plan_t pl, void* dev_ptr, int64_t bytes) {
   if (((uintptr_t)dev_ptr) & 255) return pl->fail(FDAS_ERR_ARG, "workspace must be 256-byte aligned");
   hipError_t e = hipSetDevice(pl->device);
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  // a captured search graph reads descriptors, templates and the status word
+  // of the old workspace: it is dropped with the binding
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->graph_exec = nullptr;
+  pl->graph = nullptr;
+  pl->graph_key.clear();
   pl->ws = (char*)dev_ptr;
   pl->ws_bytes = bytes;
   pl->templates_ready = false;
@@ -413,6 +425,13 @@ static fdas_status run_spectrum(fdas_plan_t pl, const float* series, void* spec_
   return FDAS_OK;
 }
 
+// The harmonic sum copies plane strips with 16-byte loads from the plane's
+// base: a plane that is only element-aligned is refused before any launch.
+static fdas_status check_harm_plane(fdas_plan_t pl, const void* plane) {
+  if (((uintptr_t)plane) & 15) return pl->fail(FDAS_ERR_ARG, "plane must be 16-byte aligned for the harmonic sum");
+  return FDAS_OK;
+}
+
 // Bytes of the packed planes of the current batch.
 static int64_t plane_need(fdas_plan_t pl) { return pl->total_bins * pl->Z * pl->res * rbytes(pl->p.plane_dtype); }
 
@@ -518,9 +537,11 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
   if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
   if (!plane || !d_count || capacity < 0 || (capacity > 0 && !cands))
     return pl->fail(FDAS_ERR_ARG, "plane and d_count are required; cands when capacity > 0");
+  fdas_status s = check_harm_plane(pl, plane);
+  if (s != FDAS_OK) return s;
   hipError_t e = hipSetDevice(pl->device);
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
-  fdas_status s = ensure_lengths(pl, lengths, n);
+  s = ensure_lengths(pl, lengths, n);
   if (s != FDAS_OK) return s;
   const HarmArgs a = harm_args(pl, plane, cands, capacity, d_count);
   if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, pl->stream)) != hipSuccess)
@@ -556,23 +577,25 @@ fdas_status fdas_search(fdas_plan_t pl, const float* series, const int64_t* offs
     return pl->fail(FDAS_ERR_ARG, "series, offsets and d_count are required; cands when capacity > 0");
   if (use_graph && pl->stream == nullptr)
     return pl->fail(FDAS_ERR_STATE, "graph mode needs a non-default stream");
+  fdas_status s = check_harm_plane(pl, plane);
+  if (s != FDAS_OK) return s;
   hipError_t e = hipSetDevice(pl->device);
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
-  fdas_status s = set_batch(pl, offsets, lengths, n);  // uploads descriptors outside any capture
+  s = set_batch(pl, offsets, lengths, n);  // uploads descriptors outside any capture
   if (s != FDAS_OK) return s;
   if (!plane || plane_bytes < plane_need(pl)) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
   void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
   if (!use_graph) return enqueue_search(pl, series, spec, plane, plane_bytes, cands, capacity, d_count);
 
-  std::vector<uintptr_t> key = {(uintptr_t)series, (uintptr_t)spec, (uintptr_t)plane, (uintptr_t)plane_bytes,
-                                (uintptr_t)cands, (uintptr_t)capacity, (uintptr_t)d_count};
+  std::vector<uintptr_t> key = {(uintptr_t)pl->ws, (uintptr_t)series, (uintptr_t)spec, (uintptr_t)plane,
+                                (uintptr_t)plane_bytes, (uintptr_t)cands, (uintptr_t)capacity, (uintptr_t)d_count};
   for (int i = 0; i < n; ++i) {
     key.push_back((uintptr_t)offsets[i]);
     key.push_back((uintptr_t)lengths[i]);
   }
   if (!pl->graph_exec || key != pl->graph_key) {
-    if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
-    if (pl->graph) hipGraphDestroy(pl->graph);
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
     pl->graph_exec = nullptr;
     pl->graph = nullptr;
     if ((e = hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
@@ -581,12 +604,12 @@ fdas_status fdas_search(fdas_plan_t pl, const float* series, const int64_t* offs
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(pl->stream, &g);
     if (s != FDAS_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return s;
     }
     if (e != hipSuccess) return hip_fail(pl, e, "end capture");
     if ((e = hipGraphInstantiate(&pl->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       return hip_fail(pl, e, "graph instantiate");
     }
     pl->graph = g;
@@ -608,8 +631,9 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
   double best_t = 1e300;
   fdas_params winner = *base;
   bool any = false;
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
     g_plan_error = "hipEventCreate failed";
     return FDAS_ERR_HIP;
   }
@@ -645,14 +669,18 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
       const int64_t len = p.n_samples;
       float best_one = 1e30f;
       for (int rep = 0; rep < 4 && s == FDAS_OK; ++rep) {
-        hipEventRecord(e0, st);
+        if (hipEventRecord(e0, st) != hipSuccess) {
+          s = FDAS_ERR_HIP;
+          break;
+        }
         s = fdas_convolve_spectrum(pl, spec, &len, 1, plane, plane_bytes);
-        hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) s = FDAS_ERR_HIP;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) best_one = std::min(best_one, ms);  // first run warms up
+        if (s == FDAS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          s = FDAS_ERR_HIP;
+        if (s == FDAS_OK && rep > 0) best_one = std::min(best_one, ms);  // first run warms up
       }
+      if (s != FDAS_OK) g_plan_error = "autotune: " + (pl->err.empty() ? std::string("a HIP event call failed") : pl->err);
       fdas_plan_destroy(pl);
       if (s != FDAS_OK) {
         result = s;
@@ -666,8 +694,8 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
     }
     if (result != FDAS_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (result != FDAS_OK) return result;
   if (!any) {
     g_plan_error = "no candidate configuration was valid";
@@ -828,13 +856,13 @@ fdas_status fdas_test_fft(fdas_plan_t pl, int32_t L, int32_t direction, const vo
 
 fdas_status fdas_plan_destroy(fdas_plan_t pl) {
   if (!pl) return FDAS_OK;
-  if (pl->graph_exec) hipGraphExecDestroy(pl->graph_exec);
-  if (pl->graph) hipGraphDestroy(pl->graph);
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->h_desc_pinned || pl->h_lists_pinned) {
-    hipSetDevice(pl->device);
-    hipStreamSynchronize(pl->stream);
-    if (pl->h_desc_pinned) hipHostFree(pl->h_desc_pinned);
-    if (pl->h_lists_pinned) hipHostFree(pl->h_lists_pinned);
+    (void)hipSetDevice(pl->device);
+    (void)hipStreamSynchronize(pl->stream);
+    if (pl->h_desc_pinned) (void)hipHostFree(pl->h_desc_pinned);
+    if (pl->h_lists_pinned) (void)hipHostFree(pl->h_lists_pinned);
   }
   delete pl;
   return FDAS_OK;

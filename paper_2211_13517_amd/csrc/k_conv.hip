@@ -17,9 +17,10 @@
 // lane of the next wavefront (through LDS in block tiles), and for the last
 // thread of the tile the first thread's next register.
 //
-// L <= 2048: one wavefront owns a tile and exchanges through its private LDS
-// buffer, so the eight wavefronts of a block never wait for each other.
-// L = 4096, 8192: a block of L/32 threads owns a tile and synchronises.
+// Every FFT holds 16 points per thread.  L = 1024: one wavefront owns a tile
+// and exchanges through its private LDS buffer, so the four wavefronts of a
+// block never wait for each other.  L = 2048, 4096, 8192: a block of L/16
+// threads (2, 4 or 8 wavefronts) owns a tile and synchronises.
 // Tiles are dealt round-robin to wavefronts (resp. blocks) of a grid sized to
 // the machine, so every unit runs the same number of tiles to within one.
 #include "fft.hpp"

@@ -247,6 +247,41 @@ def test_template_zero_drift_is_delta_and_unit_energy():
         assert np.all(np.abs(row[np.abs(q) <= h]) > 0) or z == 0
 
 
+def _fresnel_coefficients_by_fft(z, qmax, m=1 << 20):
+    """rho(q, z) for |q| <= qmax as Fourier coefficients of
+    g(u) = exp(i pi z (u - 1/2)^2) on [0, 1): midpoint sums of M and 2M points
+    by FFT, Richardson-combined (g(0) = g(1), so the midpoint error is
+    c/M^2 + O(1/M^4)).  Independent of the oracle's Fresnel evaluation."""
+    def mid(mm):
+        u = (np.arange(mm) + 0.5) / mm
+        c = np.fft.fft(np.exp(1j * np.pi * z * (u - 0.5) ** 2)) / mm
+        q = np.arange(-qmax, qmax + 1)
+        return c[q % mm] * np.exp(-1j * np.pi * q / mm)
+    return (4.0 * mid(2 * m) - mid(m)) / 3.0
+
+
+@pytest.mark.parametrize("z", [16.0, 20.0, 48.0, 96.0, -35.0, 3.5])
+def test_template_energy_and_taps_match_fine_fourier_series(z):
+    """E(z) = sum_{|q| <= h(z)} |rho(q, z)|^2, and the taps conj(rho)/sqrt(E),
+    against the Fourier coefficients of the unit-modulus chirp computed by
+    FFT: the energy the templates leave out is the chirp's spectrum beyond
+    +-h(z), so 0.99 < E < 1, falling with |z|."""
+    h = int(o.half_width(np.array([z]))[0])
+    rho = _fresnel_coefficients_by_fft(z, h)
+    e_ref = float(np.sum(np.abs(rho) ** 2))
+    e = float(o.template_energy(np.array([z]))[0])
+    assert abs(e - e_ref) < 1e-10, (z, e, e_ref)
+    assert 0.99 < e < 1.0
+    taps, hmax = o.template_taps(np.array([z]))
+    col = np.arange(-h, h + 1) + hmax
+    np.testing.assert_allclose(taps[0, col], np.conj(rho) / math.sqrt(e_ref), rtol=0, atol=1e-10)
+
+
+def test_template_energy_falls_with_drift():
+    e = o.template_energy(np.array([16.0, 20.0, 48.0, 96.0]))
+    assert np.all(np.diff(e) < 0)
+
+
 def test_ska_grid_has_193_trials():
     g = json.load(open(os.path.join(GOLDEN, "paper_numbers.json")))
     zs = o.z_grid(-96, 96, 1)
