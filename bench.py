@@ -9,11 +9,14 @@ sinusoids, already resident in HBM.  Throughput is bins x templates per second
 in bfloat16 (FP32 arithmetic); the FP32-storage path is timed beside it.
 
 Prints one JSON line.  Extra legs: the FP64 oracle timed on a bounded sample
-of the same workload on the host (cpu_baseline, the only use of the oracle
-here), the power error of the BF16 path against the FP32 path at detections,
-the recall of the injections, the energy per unit of work, the same step on a
-half-bin plane, and the refinement of 4096 off-grid candidates on a 2^22-bin
-spectrum.
+of the same workload on the host's cores (cpu_baseline, the only use of the
+oracle here), the power error of the BF16 path against the FP32-storage path
+at detections (accuracy_vs_fp32_plane; the error against the FP64 oracle is
+held by the GPU tests), the BF16 spectrum with an FP32 plane
+(bf16_in_f32_plane), the recall of the injections, the energy per unit of
+work, the same step on a half-bin plane, the refinement of 4096 off-grid
+candidates on a 2^22-bin spectrum, and the 512-trial batch of uneven DM
+trials (batch: autotuned, graph-replayed chunks).
 
 Kernel durations come from HIP events recorded on the plan's stream around
 each stage of every timed step.  The roofline object describes the kernel
@@ -53,6 +56,7 @@ def parse():
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement leg")
     ap.add_argument("--no-interbin", action="store_true", help="skip the half-bin plane leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-counter leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-trial batch leg")
     ap.add_argument("--interbin", action="store_true",
                     help="time the step on the half-bin plane (implies --only-step --no-fp32)")
     ap.add_argument("--only-step", action="store_true",
@@ -359,20 +363,75 @@ def fdas_cands(res):
     return fdas.candidates_to_numpy(res["cands"], res["count"])
 
 
-def cpu_baseline(o, x, rows=24):
-    """The oracle as it stands, timed on a bounded sample: spectrum and median
-    normalisation of the full series, then the correlation rows of `rows`
-    acceleration trials (numpy's FFT runs on one thread)."""
+# ------------------------------------------------------------ CPU baseline
+# The oracle on the host's cores: a pool of worker processes (started with
+# "spawn" before the first GPU call, so no worker inherits a GPU context),
+# each holding the series' normalised spectrum and computing whole
+# correlation rows of the plane with numpy's single-threaded FFT.
+
+_ORACLE_A = None
+
+
+def _oracle_worker_init(x, ready):
+    global _ORACLE_A
+    from oracle import fdas64 as o
+    _ORACLE_A = o.normalise(o.spectrum(x), "median")
+    ready.put(1)
+
+
+def _oracle_rows(rows):
+    from oracle import fdas64 as o
     zs = o.z_grid(-96, 96, 1)
+    p = o.power_plane(_ORACLE_A, zs, rows=list(rows))
+    return float(np.sum(p))
+
+
+def cpu_pool_start(x):
+    """Starts the oracle pool: one worker per core this process may use (at
+    most 16, the host share of one GPU), each normalising the series once."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")
+    ready = ctx.Queue()
+    # one thread per worker: the oracle's quadratures call BLAS, whose own
+    # thread pool in every worker would oversubscribe the cores many times
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in saved})
+    try:
+        pool = ctx.Pool(cores, initializer=_oracle_worker_init, initargs=(x, ready))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"pool": pool, "ready": ready, "cores": cores}
+
+
+def cpu_baseline(o, x, cp, rows_per_core=1):
+    """The oracle as it stands, timed on a bounded sample of the step: the
+    spectrum and median normalisation of the full series (one core, in this
+    process), then `rows_per_core` correlation rows per worker spread over the
+    pool (full-length FFT correlation per acceleration trial, FP64)."""
+    cores = cp["cores"]
+    for _ in range(cores):           # every worker has its spectrum
+        cp["ready"].get(timeout=600)
+    zs = o.z_grid(-96, 96, 1)
+    rows = min(len(zs), rows_per_core * cores)
     sel = np.linspace(0, len(zs) - 1, rows).round().astype(int)
     t0 = time.perf_counter()
-    a = o.normalise(o.spectrum(x), "median")
-    o.power_plane(a, zs, rows=list(sel))
-    dt = time.perf_counter() - t0
+    o.normalise(o.spectrum(x), "median")
+    t1 = time.perf_counter()
+    cp["pool"].map(_oracle_rows, [[int(j)] for j in sel], chunksize=1)
+    t2 = time.perf_counter()
+    cp["pool"].close()
+    cp["pool"].join()
     nb = len(x) // 2
-    return dict(value=rows * nb / dt, unit="bins*templates/s", cores=1, kind="oracle",
-                sample=f"spectrum+median normalisation of one N={len(x)} series and {rows} of 193 template rows "
-                       f"(full-length FFT correlation, FP64, numpy single-threaded); {dt:.1f} s")
+    dt = t2 - t0
+    return dict(value=rows * nb / dt, unit="bins*templates/s", cores=cores, kind="oracle",
+                sample=f"spectrum+median normalisation of one N={len(x)} series on 1 core ({t1 - t0:.2f} s), then "
+                       f"{rows} of its 193 template rows on {cores} worker processes ({t2 - t1:.2f} s); "
+                       f"full-length FFT correlation, FP64, numpy single-threaded per process")
 
 
 def refine_leg(torch, fdas, synth):
@@ -625,14 +684,20 @@ def main():
         args.only_step = args.no_fp32 = True
     if args.only_step:
         args.no_cpu_baseline = args.no_check = args.no_refine = args.no_interbin = args.no_energy = True
+        args.no_batch = True
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (sharding over "
                                    "GPUs is designed but not built)"}))
         sys.exit(2)
+    import synth
+    cpu = None
+    if args.workload == "ska-single":
+        x, inj, _ = synth.ska_single(seed=2, n=args.n)
+        if not args.no_cpu_baseline:
+            cpu = cpu_pool_start(x)   # before torch or the library touch the GPU
     import torch
     _torch = torch
     import paper_2211_13517_amd as fdas
-    import synth
     fdas.load()
     if args.workload in ("ska-batch", "ska-full"):
         out = (batch_leg if args.workload == "ska-batch" else full_leg)(args, torch, fdas, synth)
@@ -642,7 +707,6 @@ def main():
                 f.write(json.dumps(out) + "\n")
         return
     n = args.n
-    x, inj, _ = synth.ska_single(seed=2, n=n)
     xt = torch.from_numpy(x).to("cuda")
     plane_dt = args.plane or args.store
     res = run_path(fdas, torch, xt, n, args, args.store, plane_dt, interbin=1 if args.interbin else 0)
@@ -692,9 +756,10 @@ def main():
         alg_bps = kb["alg_bytes"] / (kb["ms"] / 1e3)
         kb["alg_frac_of_copy"] = alg_bps / copy_bw
         if kb["traffic"]:
-            kb["measured_GBps"] = kb["traffic"] / (kb["ms"] / 1e3) / 1e9
-            kb["measured_frac_of_peak"] = kb["traffic"] / (kb["ms"] / 1e3) / PEAK_HBM
-            kb["measured_frac_of_copy"] = kb["traffic"] / (kb["ms"] / 1e3) / copy_bw
+            # FETCH_SIZE/WRITE_SIZE count the bytes leaving L2 for the memory
+            # side (MALL hits included), not HBM bytes alone
+            kb["l2_miss_GBps"] = kb["traffic"] / (kb["ms"] / 1e3) / 1e9
+            kb["traffic_over_alg_bytes"] = kb["traffic"] / kb["alg_bytes"]
     out["kernels"] = {"convolve_power": conv, "harmonic_sum": harm}
     dom = harm if res["harm_ms"] > res["conv_ms"] else conv
     out["roofline"] = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
@@ -708,7 +773,15 @@ def main():
                                   "harmonic_sum": r32["harm_ms"] / res["harm_ms"]}
     if not args.no_check and not args.no_fp32 and args.store != "f32":
         tau1 = float(res["plan"].thresholds()[0])
-        out["accuracy"] = {args.store: precision_checks(res, r32, inj, Z, tau1)}
+        out["accuracy_vs_fp32_plane"] = {args.store: precision_checks(res, r32, inj, Z, tau1)}
+        if args.store == "bf16" and plane_dt == "bf16":
+            # the third storage form: BF16 spectrum and templates, FP32 plane
+            rbf = run_path(fdas, torch, xt, n, args, "bf16", "f32")
+            out["bf16_in_f32_plane"] = {
+                "value": bt / rbf["step_s"], "ms_per_step": rbf["step_s"] * 1e3, "conv_ms": rbf["conv_ms"],
+                "harmonic_sum_ms": rbf["harm_ms"], "speedup_vs_fp32_step": r32["step_s"] / rbf["step_s"],
+                "accuracy_vs_fp32_plane": precision_checks(rbf, r32, inj, Z, tau1)}
+            del rbf
     if not args.no_energy and not args.no_fp32 and args.store == "bf16":
         try:
             meter = EnergyMeter(torch)
@@ -738,15 +811,19 @@ def main():
             "recall_midway": midway_recall(torch, fdas, synth, {"bins": res, "half_bins": rib}, n)}
     if not args.no_refine:
         out["refine"] = refine_leg(torch, fdas, synth)
+    if not args.no_batch:
+        b = batch_leg(args, torch, fdas, synth)
+        out["batch"] = {k: b[k] for k in ("workload", "bt_per_s", "seconds", "recall_detectable",
+                                          "detectable_injections", "segment_len", "templates_per_tile")}
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    if not args.no_cpu_baseline:
+    if cpu is not None:
         from oracle import fdas64 as o
-        out["cpu_baseline"] = cpu_baseline(o, x)
+        out["cpu_baseline"] = cpu_baseline(o, x, cpu)
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

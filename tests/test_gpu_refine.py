@@ -1,5 +1,7 @@
 """GPU parity of the off-grid power P(r, z), its adjoint and refinement,
 through the C ABI, against the FP64 oracle evaluated on the same spectrum."""
+import math
+
 import numpy as np
 import pytest
 
@@ -279,8 +281,12 @@ def test_refine_harmonics_reaches_oracle_optimum(lib, store, H):
         assert abs(rr[i] - ro) <= 0.02, (i, rr[i], ro)
         same_piece = all(np.ceil(abs(k * zz[i]) / 2) == np.ceil(abs(k * zo) / 2) for k in range(1, H + 1))
         assert abs(zz[i] - zo) <= (0.1 if same_piece else 0.5), (i, zz[i], zo)
-        # the refined fundamental is the train's, within a bin and 1.5 z at its top harmonic
-        assert abs(rr[i] - truth[i, 0]) * H < 1.0 and abs(zz[i] - truth[i, 1]) * H < 1.5
+        # the refined fundamental is the train's, within a bin and 1.5 z at its top harmonic up
+        # to H = 8; with amplitudes falling as 1/k every harmonic adds the same z curvature at
+        # the fundamental, so the noise error there shrinks only as 1/sqrt(H) while the top
+        # harmonic multiplies it by H: the z bound grows as sqrt(H / 8) above H = 8
+        zb = 1.5 * max(1.0, math.sqrt(H / 8.0))
+        assert abs(rr[i] - truth[i, 0]) * H < 1.0 and abs(zz[i] - truth[i, 1]) * H < zb
 
 
 def test_invalid_positions_give_nan(lib):
