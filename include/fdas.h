@@ -313,6 +313,21 @@ int64_t fdas_cluster_scratch_bytes(int64_t capacity);
 fdas_status fdas_cluster(fdas_plan_t plan, const fdas_candidate *cands, const int64_t *d_count, int64_t capacity,
                          int32_t radius_r, int32_t radius_j, void *scratch, int64_t scratch_bytes, uint8_t *keep);
 
+/* Candidate clustering without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): exactly fdas_cluster, with its hash table
+ * in a static device array of the library (24 MiB on each GPU it runs on,
+ * reserved when the library's code is loaded there and held until the process
+ * ends) instead of caller scratch.  capacity at most 2^20 records
+ * (FDAS_ERR_ARG above that: use fdas_cluster).  The table's device address is
+ * looked up once per device when a plan is made there.  Every call on one GPU
+ * shares that GPU's table and clears it (with a fill kernel) before use, so
+ * calls that overlap on one GPU (two plans on different streams, or two host
+ * threads) race and must be ordered by the caller.  Calls no hipMalloc or
+ * hipFree. */
+fdas_status fdas_cluster_noalloc(fdas_plan_t plan, const fdas_candidate *cands, const int64_t *d_count,
+                                 int64_t capacity, int32_t radius_r, int32_t radius_j, uint8_t *keep);
+
 /* Self-test hook of the FFT engine: `batch` independent complex FFTs of
  * length L (256 ... 8192) from `in` to `out` (device, complex64, contiguous),
  * direction -1: X_k = sum_n x_n exp(-2 pi i k n / L), +1: the unnormalised

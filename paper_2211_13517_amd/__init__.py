@@ -52,7 +52,8 @@ EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace
            "fdas_spectrum", "fdas_convolve_spectrum", "fdas_convolve", "fdas_harmonic_sum", "fdas_check",
            "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
-           "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster", "fdas_refine_harmonics"]
+           "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster", "fdas_refine_harmonics",
+           "fdas_cluster_noalloc"]
 
 _lib = None
 
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
         "fdas_copy_thresholds": ([P, POINTER(c_double)], c_int),
         "fdas_cluster_scratch_bytes": ([c_int64], c_int64),
         "fdas_cluster": ([P, P, P, c_int64, c_int32, c_int32, P, c_int64, P], c_int),
+        "fdas_cluster_noalloc": ([P, P, P, c_int64, c_int32, c_int32, P], c_int),
         "fdas_test_fft": ([P, c_int32, c_int32, P, P, c_int64], c_int),
         "fdas_plan_destroy": ([P], c_int),
         "fdas_last_error": ([P], c_char_p),
@@ -270,6 +272,18 @@ class Plan:
         self._check(self.lib.fdas_cluster(self.handle, c_void_p(cands.data_ptr()), c_void_p(count.data_ptr()), cap,
                                           radius_r, radius_j, c_void_p(self._cluster_scratch.data_ptr()), nbytes,
                                           c_void_p(keep.data_ptr())))
+        return keep
+
+    def cluster_noalloc(self, cands, count, radius_r: int = 2, radius_j: int = 2, keep=None):
+        """fdas_cluster through the library's static table (no device allocation
+        by the library; at most 2^20 records).  ``keep``: optional uint8
+        device tensor [capacity] to write into."""
+        import torch
+        cap = int(cands.shape[0])
+        if keep is None:
+            keep = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.fdas_cluster_noalloc(self.handle, c_void_p(cands.data_ptr()), c_void_p(count.data_ptr()),
+                                                  cap, radius_r, radius_j, c_void_p(keep.data_ptr())))
         return keep
 
     def check(self, count=None, capacity: int = 0):

@@ -93,6 +93,7 @@ struct fdas_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uintptr_t> graph_key;
+  hipError_t static_table_status = hipSuccess;  // look-up of the static clustering table at plan time
 
   fdas_status fail(fdas_status s, const std::string& m) {
     err = m;
@@ -203,6 +204,11 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
     delete pl;
     return bad("could not query the device's compute-unit count");
   }
+  // set-up of the allocation-free clustering: the static table's address on
+  // this device (looked up once per device; a failure is reported by that
+  // entry point, the others do not need it)
+  void* unused_table = nullptr;
+  pl->static_table_status = cluster_static_scratch(device, &unused_table);
 
   // workspace layout
   int64_t o = 0;
@@ -768,6 +774,28 @@ fdas_status fdas_cluster(fdas_plan_t pl, const fdas_candidate* cands, const int6
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
   e = launch_cluster(cands, reinterpret_cast<const unsigned long long*>(d_count), capacity, radius_r, radius_j,
                      scratch, keep, pl->cu_count, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "cluster");
+  return FDAS_OK;
+}
+
+fdas_status fdas_cluster_noalloc(fdas_plan_t pl, const fdas_candidate* cands, const int64_t* d_count, int64_t capacity,
+                                 int32_t radius_r, int32_t radius_j, uint8_t* keep) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!d_count || capacity < 0 || (capacity > 0 && (!cands || !keep)))
+    return pl->fail(FDAS_ERR_ARG, "d_count is required; cands and keep when capacity > 0");
+  if (radius_r < 0 || radius_r > 64 || radius_j < 0 || radius_j > 64)
+    return pl->fail(FDAS_ERR_ARG, "radius_r and radius_j must be in [0, 64]");
+  if (capacity > kClusterStaticMaxRecords)
+    return pl->fail(FDAS_ERR_ARG, "fdas_cluster_noalloc takes at most " + std::to_string(kClusterStaticMaxRecords) +
+                                      " records (capacity " + std::to_string(capacity) + "); use fdas_cluster");
+  if (capacity == 0) return FDAS_OK;
+  if (pl->static_table_status != hipSuccess) return hip_fail(pl, pl->static_table_status, "static table look-up");
+  void* table = nullptr;
+  hipError_t e = cluster_static_scratch(pl->device, &table);  // the address found at plan time
+  if (e != hipSuccess) return hip_fail(pl, e, "static table look-up");
+  if ((e = hipSetDevice(pl->device)) != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  e = launch_cluster(cands, reinterpret_cast<const unsigned long long*>(d_count), capacity, radius_r, radius_j, table,
+                     keep, pl->cu_count, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "cluster");
   return FDAS_OK;
 }

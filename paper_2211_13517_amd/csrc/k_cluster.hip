@@ -5,9 +5,11 @@
 // no record of the same series within |dR| <= rr and |dj| <= rj has a larger
 // Gaussian significance; equal significances go to the smaller (j, R).  The
 // neighbourhood lookup uses an open-addressing hash table of the records'
-// cells in caller scratch memory: a fill, one insert pass and one probe pass,
-// each a plain grid over the records (their number is read on the device).
+// cells in scratch memory (the caller's, or this file's static array for the
+// allocation-free variant): a fill, one insert pass and one probe pass, each
+// a plain grid over the records (their number is read on the device).
 #include <algorithm>
+#include <mutex>
 
 #include "launch.hpp"
 
@@ -92,11 +94,45 @@ int64_t cluster_scratch_bytes(int64_t capacity) {
   return t * (int64_t)sizeof(unsigned long long) + t * (int64_t)sizeof(int32_t);
 }
 
+// Scratch of the allocation-free variant: one table for kClusterStaticMaxRecords
+// records (2^21 slots of an 8-byte key and a 4-byte index, 24 MiB), a copy
+// per GPU that the library runs on, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel: its device address comes from
+// hipGetSymbolAddress, per device.
+constexpr int64_t kClusterStaticBytes = (int64_t(2) << 20) * 12;
+__device__ __align__(256) unsigned char scratch[kClusterStaticBytes];
+
+hipError_t cluster_static_scratch(int device, void** ptr) {
+  static_assert((int64_t(1) << 21) * 12 == kClusterStaticBytes, "table size");
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    addr[device] = a;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
 hipError_t launch_cluster(const fdas_candidate* c, const unsigned long long* count, int64_t capacity, int rr, int rj,
-                          void* scratch, uint8_t* keep, int cus, hipStream_t st) {
+                          void* table, uint8_t* keep, int cus, hipStream_t st) {
   const int log2t = cluster_log2_slots(capacity);
   const int64_t t = 1ll << log2t;
-  auto* keys = reinterpret_cast<unsigned long long*>(scratch);
+  auto* keys = reinterpret_cast<unsigned long long*>(table);
   auto* idx = reinterpret_cast<int32_t*>(keys + t);
   const int grid_t = (int)std::min<int64_t>((t + 255) / 256, (int64_t)cus * 8);
   const int grid_c = (int)std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, (int64_t)cus * 8));

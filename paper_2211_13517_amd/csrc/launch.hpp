@@ -101,9 +101,12 @@ hipError_t launch_refine_harmonics(int sdt, const void* spec, int64_t nb, double
                                    int64_t n, int iters, int margin, double* p_final, hipStream_t st);
 
 // candidate clustering
+constexpr int64_t kClusterStaticMaxRecords = int64_t(1) << 20;  // capacity of the static-scratch variant
 int64_t cluster_scratch_bytes(int64_t capacity);
+// device address of the static clustering scratch on `device` (looked up once per device)
+hipError_t cluster_static_scratch(int device, void** ptr);
 hipError_t launch_cluster(const fdas_candidate* c, const unsigned long long* count, int64_t capacity, int rr, int rj,
-                          void* scratch, uint8_t* keep, int cus, hipStream_t st);
+                          void* table, uint8_t* keep, int cus, hipStream_t st);
 
 // small helpers (fill kernels are graph-capture safe, unlike memset nodes)
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t value, hipStream_t st);
