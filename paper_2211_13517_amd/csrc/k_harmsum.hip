@@ -185,6 +185,44 @@ __device__ __forceinline__ void stage_sums(const HarmVals<H>& x, SINK sink) {
   }
 }
 
+// Wave-wide pass mask of one trial: the OR over stages of the ballots
+// S_st >= thr[st], each ballot the compare's own lane mask.  On 16-bit planes
+// stage 0 (harmonic H alone, a stored value) is tested on its raw bits: for
+// non-negative values the bit patterns order like the values, so
+// x >= thr[0]  <=>  bits(x) >= thr0_bits, the smallest pattern whose value is
+// at least thr[0].  (A NaN pattern also passes this test; the exact stage
+// tests of the reporting pass then reject it, as the float compare does.)
+template <int PDT, int H>
+__device__ __forceinline__ unsigned long long pass_mask(const HarmVals<H>& x, const float* thr, uint32_t thr0_bits) {
+  unsigned long long m = 0;
+  if constexpr (Store<PDT>::RBYTES == 2) {
+    m = __builtin_amdgcn_ballot_w64(x.v[H - 1] >= thr0_bits);
+    stage_sums<PDT, H>(x, [&](int st, float S) {
+      if (st > 0) m |= __builtin_amdgcn_ballot_w64(S >= thr[st]);
+    });
+  } else {
+    stage_sums<PDT, H>(x, [&](int st, float S) { m |= __builtin_amdgcn_ballot_w64(S >= thr[st]); });
+  }
+  return m;
+}
+
+// Smallest 16-bit pattern of the plane type whose value is >= v (v > 0, or +inf).
+template <int PDT>
+__device__ __forceinline__ uint32_t ceil_bits16(float v) {
+  if constexpr (PDT == FDAS_BF16) {
+    uint32_t b = __float_as_uint(v) >> 16;
+    if (__uint_as_float(b << 16) < v) ++b;
+    return b;
+  } else if constexpr (PDT == FDAS_F16) {
+    const _Float16 h = (_Float16)v;
+    uint32_t b = __builtin_bit_cast(uint16_t, h);
+    if ((float)h < v) ++b;
+    return b;
+  } else {
+    return 0u;
+  }
+}
+
 template <int PDT, int H>
 __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   using PS = Store<PDT>;
@@ -291,6 +329,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     en[st] = R >= (1 << st) * a.r_lo;
     thr[st] = en[st] ? a.tau[st] : __builtin_inff();
   }
+  const uint32_t thr0_bits = ceil_bits16<PDT>(thr[0]);
   // wave-wide pass masks per trial (scalar registers)
   unsigned long long bal[kBand];
   auto band = [&](auto negc) {
@@ -315,11 +354,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
         nxt = load_vals<PDT, H, HT::KL>(lds, boff, offs(std::integral_constant<int, t + 1>{}),
                                         dir(std::integral_constant<int, t + 1>{}));
       bal[t] = 0;
-      if (t >= t_lo && t < t_hi) {
-        bool pass = false;
-        stage_sums<PDT, H>(cur, [&](int st, float S) { pass |= S >= thr[st]; });
-        bal[t] = __ballot(pass);
-      }
+      if (t >= t_lo && t < t_hi) bal[t] = pass_mask<PDT, H>(cur, thr, thr0_bits);
       if constexpr (t + 1 < kBand) cur = nxt;
     });
   };
