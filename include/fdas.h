@@ -226,7 +226,13 @@ fdas_status fdas_rz_power(fdas_plan_t plan, const void *spectrum, int64_t n_bins
  * dy/dz = sum A_k conj(d rho/dz), FP64), and, if grad_spectrum is non-NULL,
  * overwrites it (complex64 [n_bins]) with sum_i grad_p[i] 2 y_i rho(k - r_i, z_i),
  * the gradient with respect to A_k as d/dRe + i d/dIm.  That sum is formed in
- * 2^-40 fixed point with integer atomics, so it is bitwise deterministic.
+ * fixed point with integer atomics, so it is bitwise deterministic, at a unit
+ * 2^-s chosen per call that no partial sum can overflow: |rho| <= 1, so every
+ * term of candidate i is at most b_i = 2 |grad_p[i]| |y_i|, and s is the
+ * largest integer <= 40 with n max_i b_i 2^s <= 2^61 (|dP/dA| of any size
+ * keeps 2^-61 of n max_i b_i as its resolution).  A term that is not finite
+ * (non-finite grad_p or y) is left out and reported by fdas_check as
+ * FDAS_ERR_NONFINITE.
  * y: the forward's y_out, or NULL to recompute it.  Uses the workspace. */
 fdas_status fdas_rz_power_grad(fdas_plan_t plan, const void *spectrum, int64_t n_bins, const double *r,
                                const double *z, const void *y, const double *grad_p, int64_t n, double *grad_r,

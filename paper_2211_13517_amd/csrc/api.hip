@@ -733,6 +733,8 @@ fdas_status fdas_check(fdas_plan_t pl, const int64_t* d_count, int64_t capacity)
     if (e != hipSuccess) return hip_fail(pl, e, "status clear");
   }
   if (st & 1) return pl->fail(FDAS_ERR_NONFINITE, "a spectrum contained NaN or Inf");
+  if (st & 2)
+    return pl->fail(FDAS_ERR_NONFINITE, "a spectrum-gradient term was not finite (skipped): non-finite grad_p or y");
   if (d_count && cnt > capacity)
     return pl->fail(FDAS_ERR_OVERFLOW, "candidate buffer overflow: " + std::to_string(cnt) + " passing cells, capacity " +
                                            std::to_string(capacity));
@@ -836,8 +838,13 @@ fdas_status fdas_rz_power_grad(fdas_plan_t pl, const void* spec, int64_t nb, con
   if (n == 0) return FDAS_OK;
   if (!r || !z || !grad_p || !grad_r || !grad_z) return pl->fail(FDAS_ERR_ARG, "r, z, grad_p, grad_r, grad_z are required");
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(pl->ws + pl->off_Y);
+  // status word at byte 0 of the status block, the gradient bound at 8 and the
+  // fixed-point unit at 16
+  int32_t* status = reinterpret_cast<int32_t*>(pl->ws + pl->off_status);
+  unsigned long long* max_bits = reinterpret_cast<unsigned long long*>(pl->ws + pl->off_status + 8);
+  double* scale = reinterpret_cast<double*>(pl->ws + pl->off_status + 16);
   hipError_t e = launch_rz_grad(pl->p.store_dtype, spec, nb, r, z, (const c64*)y, grad_p, n, pl->p.kernel_margin, grad_r,
-                                grad_z, (float*)grad_spectrum, acc, pl->stream);
+                                grad_z, (float*)grad_spectrum, acc, max_bits, scale, status, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "rz power grad");
   return FDAS_OK;
 }

@@ -169,12 +169,50 @@ __global__ __launch_bounds__(256) void k_rz_power(const void* spec, int64_t nb, 
   }
 }
 
-constexpr double kFixScale = 1099511627776.0;  // 2^40: fixed-point unit of the spectrum-gradient accumulator
+// The spectrum gradient dP/dA_k = sum_c 2 g_c y_c rho(k - r_c, z_c) is summed
+// in fixed point with 64-bit integer atomics: integer addition is
+// associative, so the sum does not depend on the arrival order.  Its unit
+// 2^-s is chosen per call from a bound on the terms, so that no partial sum
+// can overflow: |rho| <= 1 (an average of unit-modulus values), hence every
+// term of candidate c is at most b_c = 2 |g_c| |y_c| and every partial sum at
+// most n max_c b_c; s is the largest integer <= 40 with
+// n max_c b_c 2^s <= 2^61 (one bit of slack for rounding).  The maximum is
+// taken with an integer atomic on the (non-negative) doubles' bit patterns,
+// so it too is order-independent.  Terms that are not finite are skipped and
+// latched (status bit 2).
+constexpr int kFixMaxShift = 40;
+
+template <int SDT>
+__global__ __launch_bounds__(256) void k_grad_bound(const void* spec, int64_t nb, const double* r, const double* z,
+                                                    const c64* y_in, const double* gp, int64_t n, int margin,
+                                                    unsigned long long* max_bits, int32_t* status) {
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  const double rr = r[c], zz = z[c];
+  if (!rz_valid(rr, zz)) return;  // such a candidate adds nothing to the spectrum gradient
+  const c64 y = y_in ? y_in[c] : rz_eval<SDT, false>(spec, nb, rr, zz, margin).y;
+  if ((threadIdx.x & 63) != 0) return;
+  const double b = 2.0 * fabs(gp[c]) * sqrt(y.re * y.re + y.im * y.im);
+  if (!isfinite(b)) {
+    atomicOr(status, 2);
+    return;
+  }
+  atomicMax(max_bits, (unsigned long long)__double_as_longlong(b));
+}
+
+__global__ void k_grad_scale(const unsigned long long* max_bits, int64_t n, double* scale) {
+  const double t = (double)n * __longlong_as_double((long long)*max_bits);
+  int sh = kFixMaxShift;
+  if (!(t < 1e300)) sh = -1000;  // absurd terms: every partial sum stays far below 2^61
+  else if (t > 0.0) sh = min(kFixMaxShift, 61 - (ilogb(t) + 1));  // t < 2^(ilogb(t) + 1)
+  *scale = ldexp(1.0, sh);
+}
 
 template <int SDT>
 __global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, const double* r, const double* z,
                                                  const c64* y_in, const double* gp, int64_t n, int margin,
-                                                 double* gr, double* gz, unsigned long long* acc) {
+                                                 double* gr, double* gz, unsigned long long* acc,
+                                                 const double* scale_p, int32_t* status) {
   const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n) return;
   const double rr = r[c], zz = z[c];
@@ -186,16 +224,20 @@ __global__ __launch_bounds__(256) void k_rz_grad(const void* spec, int64_t nb, c
     gz[c] = g * 2.0 * (y.re * e.dydz.re + y.im * e.dydz.im);
   }
   if (!acc || !rz_valid(rr, zz)) return;
-  // dP/dA_k = 2 y rho(k - r, z), accumulated in 2^-40 fixed point: integer
-  // addition is associative, so the sum does not depend on arrival order.
+  const double scale = *scale_p;
   const int64_t k0 = (int64_t)floor(rr);
   const int w = margin + (int)ceil(fabs(zz) * 0.5);
   for (int t = threadIdx.x & 63; t < 2 * w; t += 64) {
     const int64_t k = k0 - w + 1 + t;
     if (k < 0 || k >= nb) continue;
     const c64 v = c64scale(c64mul(y, response64((double)k - rr, zz)), 2.0 * g);
-    atomicAdd(acc + 2 * k, (unsigned long long)(long long)llrint(v.re * kFixScale));
-    atomicAdd(acc + 2 * k + 1, (unsigned long long)(long long)llrint(v.im * kFixScale));
+    const double a = v.re * scale, b = v.im * scale;
+    if (!(fabs(a) <= 4611686018427387904.0 && fabs(b) <= 4611686018427387904.0)) {  // 2^62; also NaN
+      atomicOr(status, 2);
+      continue;
+    }
+    atomicAdd(acc + 2 * k, (unsigned long long)(long long)llrint(a));
+    atomicAdd(acc + 2 * k + 1, (unsigned long long)(long long)llrint(b));
   }
 }
 
@@ -204,9 +246,10 @@ __global__ void k_fix_clear(unsigned long long* acc, int64_t n) {
     acc[i] = 0ull;
 }
 
-__global__ void k_fix_to_float(const unsigned long long* acc, float* out, int64_t n) {
+__global__ void k_fix_to_float(const unsigned long long* acc, float* out, int64_t n, const double* scale_p) {
+  const double inv = 1.0 / *scale_p;  // a power of two: exact
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = (float)((double)(long long)acc[i] / kFixScale);
+    out[i] = (float)((double)(long long)acc[i] * inv);
 }
 
 // Preconditioned gradient ascent: near a peak P ~ P0 (1 - a dr^2 - b dz^2)
@@ -428,19 +471,28 @@ hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* 
 
 hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r, const double* z, const c64* y,
                           const double* gp, int64_t n, int margin, double* gr, double* gz, float* gspec,
-                          unsigned long long* acc, hipStream_t st) {
+                          unsigned long long* acc, unsigned long long* max_bits, double* scale, int32_t* status,
+                          hipStream_t st) {
   const dim3 g((unsigned)((n + 3) / 4));
   if (gspec) {
     hipLaunchKernelGGL(k_fix_clear, dim3(1024), dim3(256), 0, st, acc, 2 * nb);
+    hipLaunchKernelGGL(k_fix_clear, dim3(1), dim3(64), 0, st, max_bits, (int64_t)1);
+    switch (sdt) {
+      case FDAS_F32: hipLaunchKernelGGL((k_grad_bound<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, max_bits, status); break;
+      case FDAS_BF16: hipLaunchKernelGGL((k_grad_bound<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, max_bits, status); break;
+      case FDAS_F16: hipLaunchKernelGGL((k_grad_bound<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, max_bits, status); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_grad_scale, dim3(1), dim3(1), 0, st, max_bits, n, scale);
   }
   unsigned long long* a = gspec ? acc : nullptr;
   switch (sdt) {
-    case FDAS_F32: hipLaunchKernelGGL((k_rz_grad<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
-    case FDAS_BF16: hipLaunchKernelGGL((k_rz_grad<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
-    case FDAS_F16: hipLaunchKernelGGL((k_rz_grad<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a); break;
+    case FDAS_F32: hipLaunchKernelGGL((k_rz_grad<FDAS_F32>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a, scale, status); break;
+    case FDAS_BF16: hipLaunchKernelGGL((k_rz_grad<FDAS_BF16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a, scale, status); break;
+    case FDAS_F16: hipLaunchKernelGGL((k_rz_grad<FDAS_F16>), g, dim3(256), 0, st, spec, nb, r, z, y, gp, n, margin, gr, gz, a, scale, status); break;
     default: return hipErrorInvalidValue;
   }
-  if (gspec) hipLaunchKernelGGL(k_fix_to_float, dim3(1024), dim3(256), 0, st, acc, gspec, 2 * nb);
+  if (gspec) hipLaunchKernelGGL(k_fix_to_float, dim3(1024), dim3(256), 0, st, acc, gspec, 2 * nb, scale);
   return hipGetLastError();
 }
 

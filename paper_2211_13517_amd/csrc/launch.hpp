@@ -92,9 +92,11 @@ hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, hipStream_t st);
 // off-grid power and refinement
 hipError_t launch_rz_power(int sdt, const void* spec, int64_t nb, const double* r, const double* z, int64_t n, int margin,
                            double* p, c64* y, hipStream_t st);
+// acc: 2 nb fixed-point words; max_bits, scale: one word each (set here)
 hipError_t launch_rz_grad(int sdt, const void* spec, int64_t nb, const double* r, const double* z, const c64* y,
                           const double* gp, int64_t n, int margin, double* gr, double* gz, float* gspec,
-                          unsigned long long* acc, hipStream_t st);
+                          unsigned long long* acc, unsigned long long* max_bits, double* scale, int32_t* status,
+                          hipStream_t st);
 hipError_t launch_refine(int sdt, const void* spec, int64_t nb, double* r, double* z, int64_t n, int iters, int margin,
                          double* p_final, hipStream_t st);
 hipError_t launch_refine_harmonics(int sdt, const void* spec, int64_t nb, double* r, double* z, const int32_t* harm,

@@ -312,3 +312,46 @@ def test_invalid_positions_give_nan(lib):
     r2, z2, S = pl.refine_harmonics(spec, torch.tensor([500.0], dtype=torch.float64, device="cuda"),
                                     torch.tensor([70000.0], dtype=torch.float64, device="cuda"), 16, n_iter=3)
     assert np.isnan(S.cpu().numpy()).all()   # harmonic 2 already lies at z = 140000
+
+
+def test_spectrum_gradient_of_large_terms_does_not_overflow(lib):
+    """Terms far beyond 2^23 (spectrum scaled by 10^4, grad_p up to 10^3:
+    sums ~ 4e7): the fixed-point unit shrinks so that no sum
+    overflows, and grad_spectrum matches the oracle's gradient to 1e-5 of
+    its largest value, bit for bit the same in a second call; a NaN grad_p
+    leaves its terms out and is reported, the other candidates' terms stay."""
+    import torch
+    n = 1 << 18
+    say("fdas_rz_power_grad large terms", n)
+    pl, spec, a, truths, starts = setup(lib, n, 24, 44)
+    spec_big = spec * 1.0e4
+    a_big = spec_big.cpu().numpy().astype(np.float64)
+    a_big = a_big[:, 0] + 1j * a_big[:, 1]
+    r = torch.tensor(starts[:, 0], dtype=torch.float64, device="cuda")
+    z = torch.tensor(starts[:, 1], dtype=torch.float64, device="cuda")
+    gp = torch.linspace(1.0, 1000.0, len(starts), device="cuda", dtype=torch.float64)
+    p, y = pl.rz_power(spec_big, r, z)
+    gr, gz, gs = pl.rz_power_grad(spec_big, r, z, gp, y=y)
+    _, _, gs2 = pl.rz_power_grad(spec_big, r, z, gp)   # y recomputed
+    pl.check()
+    assert torch.equal(gs, gs2)
+    gs = gs.cpu().numpy().astype(np.complex128)
+    rf, zf, g = r.cpu().numpy(), z.cpu().numpy(), gp.cpu().numpy()
+    want = np.zeros(len(a_big), complex)
+    for i in range(len(starts)):
+        _, _, _, ks, ga = o.rz_power_grad(a_big, rf[i], zf[i])
+        want[ks] += g[i] * ga
+    big = np.abs(want).max()
+    assert big > 2.0 ** 23          # a fixed 2^-40 unit would have overflowed
+    np.testing.assert_allclose(gs, want, rtol=0, atol=1e-5 * big)
+    # a NaN upstream gradient: reported, its terms left out
+    gp_nan = gp.clone()
+    gp_nan[0] = float("nan")
+    _, _, gs3 = pl.rz_power_grad(spec_big, r, z, gp_nan, y=y)
+    with pytest.raises(lib.FdasError, match="not finite"):
+        pl.check()
+    pl.check()
+    _, _, _, ks0, ga0 = o.rz_power_grad(a_big, rf[0], zf[0])
+    want3 = want.copy()
+    want3[ks0] -= g[0] * ga0
+    np.testing.assert_allclose(gs3.cpu().numpy().astype(np.complex128), want3, rtol=0, atol=1e-5 * big)
