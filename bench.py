@@ -630,7 +630,7 @@ def batch_leg(args, torch, fdas, synth):
     with torch.cuda.stream(stream):
         pl = fdas.Plan(store=args.store, plane=args.plane or args.store, n_samples=N, max_batch_samples=chunk_samples,
                        z_min=-96.0, z_max=96.0, z_step=1.0, n_harmonics=16, segment_len=tuned.segment_len,
-                       templates_per_tile=tuned.templates_per_tile, stream=stream)
+                       templates_per_tile=tuned.templates_per_tile, fft_radix=tuned.fft_radix, stream=stream)
         work = torch.empty(chunk_samples, dtype=torch.float32, device="cuda")
         plane = pl.new_plane(chunk_samples // 2)
         cap = 1 << 23  # strong injections leave ~10^5 passing cells each
@@ -672,7 +672,7 @@ def batch_leg(args, torch, fdas, synth):
     return {"workload": "512 uneven DM trials (256 x 2^23, 128 x 2^22, 128 x 2^21), 16 graph replays of "
                         "32-series chunks, 193 templates, harmonic sums to 16, 6 sigma",
             "bt_per_s": bt / dt, "seconds": dt, "bins_x_templates": bt, "segment_len": pl.L,
-            "templates_per_tile": int(tuned.templates_per_tile), "autotuned": True,
+            "templates_per_tile": int(tuned.templates_per_tile), "fft_radix": int(tuned.fft_radix), "autotuned": True,
             "recall_detectable": (hit / det) if det else None, "detectable_injections": det,
             "injections": sum(len(t) for t in truths)}
 
@@ -814,7 +814,8 @@ def main():
     if not args.no_batch:
         b = batch_leg(args, torch, fdas, synth)
         out["batch"] = {k: b[k] for k in ("workload", "bt_per_s", "seconds", "recall_detectable",
-                                          "detectable_injections", "segment_len", "templates_per_tile")}
+                                          "detectable_injections", "segment_len", "templates_per_tile",
+                                          "fft_radix")}
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

@@ -84,7 +84,8 @@ typedef struct {
   int32_t r_lo;              /* lowest fundamental bin searched; 0 means h_max */
   int32_t templates_per_tile; /* templates one wavefront runs per loaded segment; 0 = automatic */
   int32_t interbin;          /* 0: plane at bin resolution; 1: half-bin plane (below) */
-  int32_t reserved;          /* must be 0 */
+  int32_t fft_radix;         /* radix of the convolution FFT's passes: 0 or 16 (default), 8 or 4 at
+                                segment_len 1024 (passes 8 8 8 2, or five of 4); fdas_autotune picks it */
 } fdas_params;
 
 /* Half-bin plane (interbin = 1; the paper works at whole bins, this sub-bin
@@ -277,9 +278,25 @@ fdas_status fdas_search(fdas_plan_t plan, const float *series, const int64_t *of
                         int64_t plane_bytes, fdas_candidate *cands, int64_t capacity, int64_t *d_count,
                         int32_t use_graph);
 
+/* The whole search for a batch of any size within a plane buffer of
+ * plane_bytes (the HBM budget): the series are taken in consecutive chunks,
+ * each the longest run whose samples fit max_batch_samples and whose planes
+ * fit plane_bytes, and every chunk runs as fdas_search (spectrum in the
+ * workspace; no graph).  *d_count is reset once (with a kernel) and counts
+ * the passing cells of every chunk; the records' series field is the index
+ * in offsets/lengths.  The planes are overwritten chunk by chunk (the last
+ * chunk's remain).  n_chunks (host, optional) receives the number of chunks.
+ * Every argument is checked before any work: a series whose plane alone
+ * exceeds plane_bytes is FDAS_ERR_NOMEM.  Waits for the plan's stream before
+ * each chunk's descriptors are uploaded (the previous chunk's work). */
+fdas_status fdas_search_chunked(fdas_plan_t plan, const float *series, const int64_t *offsets_host,
+                                const int64_t *lengths_host, int32_t n_series, void *plane_out, int64_t plane_bytes,
+                                fdas_candidate *cands, int64_t capacity, int64_t *d_count, int32_t *n_chunks_host);
+
 /* Tuning: times the convolution of one full-length noise spectrum
  * for every segment length L in {1024, 2048, 4096, 8192} allowed by the z
- * range and templates_per_tile in {auto, 12, 24, 48, 96} on `device`/`hip_stream`,
+ * range, templates_per_tile in {auto, 12, 24, 48, 96} and FFT radix plan
+ * (fft_radix 16, and 8 and 4 at L = 1024) on `device`/`hip_stream`,
  * using `scratch` (device memory, at least workspace + spectrum + plane of one
  * series; FDAS_ERR_NOMEM names the size), and writes the fastest parameters
  * to *best (and its time in ms to *best_ms).  Blocks until done. */

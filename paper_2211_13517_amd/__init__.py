@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
                 ("n_harmonics", c_int32), ("kernel_margin", c_int32), ("segment_len", c_int32),
                 ("store_dtype", c_int32), ("plane_dtype", c_int32), ("norm", c_int32),
                 ("norm_block", c_int32), ("noise_var", c_double), ("sigma_threshold", c_double),
-                ("r_lo", c_int32), ("templates_per_tile", c_int32), ("interbin", c_int32), ("reserved", c_int32)]
+                ("r_lo", c_int32), ("templates_per_tile", c_int32), ("interbin", c_int32), ("fft_radix", c_int32)]
 
 
 EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace", "fdas_make_templates",
@@ -53,7 +53,7 @@ EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace
            "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
            "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster", "fdas_refine_harmonics",
-           "fdas_cluster_noalloc"]
+           "fdas_cluster_noalloc", "fdas_search_chunked"]
 
 _lib = None
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
         "fdas_refine_harmonics": ([P, P, c_int64, P, P, P, c_int64, c_int32, P], c_int),
         "fdas_search": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64, P, c_int64, P, c_int32],
                         c_int),
+        "fdas_search_chunked": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, c_int64, P, c_int64, P,
+                                 POINTER(c_int32)], c_int),
         "fdas_autotune": ([POINTER(Params), c_int, P, P, c_int64, POINTER(Params), POINTER(c_double)], c_int),
         "fdas_copy_templates": ([P, P, P], c_int),
         "fdas_copy_thresholds": ([P, POINTER(c_double)], c_int),
@@ -260,6 +262,17 @@ class Plan:
                                          c_void_p(plane.data_ptr()), nbytes, c_void_p(cands.data_ptr()),
                                          cands.shape[0], c_void_p(count.data_ptr()), 1 if use_graph else 0))
 
+    def search_chunked(self, series, offsets: Sequence[int], lengths: Sequence[int], plane, cands, count) -> int:
+        """The whole search over any number of series within ``plane``'s size
+        (fdas_search_chunked); returns the number of chunks."""
+        nbytes = plane.numel() * plane.element_size()
+        nch = c_int32()
+        self._check(self.lib.fdas_search_chunked(self.handle, c_void_p(series.data_ptr()), _i64(offsets),
+                                                 _i64(lengths), len(lengths), c_void_p(plane.data_ptr()), nbytes,
+                                                 c_void_p(cands.data_ptr()), cands.shape[0],
+                                                 c_void_p(count.data_ptr()), byref(nch)))
+        return nch.value
+
     def cluster(self, cands, count, radius_r: int = 2, radius_j: int = 2):
         """Local maxima among candidate records (see fdas_cluster): returns a
         uint8 device tensor [capacity], 1 for records to keep."""
@@ -364,7 +377,7 @@ class Plan:
 
 
 def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) -> Params:
-    """Fastest (segment_len, templates_per_tile) for the given parameters, measured
+    """Fastest (segment_len, templates_per_tile, fft_radix) for the given parameters, measured
     by fdas_autotune on this GPU; cached as JSON keyed by device and shape."""
     import json
     import torch
@@ -388,8 +401,9 @@ def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) ->
             table = json.load(open(cache))
         except (OSError, ValueError):
             table = {}
-    if key in table:
+    if key in table and "fft_radix" in table[key]:
         p.segment_len, p.templates_per_tile = table[key]["segment_len"], table[key]["templates_per_tile"]
+        p.fft_radix = table[key]["fft_radix"]
         return p
     st = stream if stream is not None else torch.cuda.current_stream(device)
     nb = p.n_samples // 2
@@ -401,7 +415,8 @@ def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) ->
                             byref(best), byref(ms))
     if st_ != 0:
         raise FdasError(st_, lib.fdas_last_error(None).decode())
-    table[key] = {"segment_len": best.segment_len, "templates_per_tile": best.templates_per_tile, "conv_ms": ms.value}
+    table[key] = {"segment_len": best.segment_len, "templates_per_tile": best.templates_per_tile,
+                  "fft_radix": best.fft_radix, "conv_ms": ms.value}
     try:
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         json.dump(table, open(cache, "w"), indent=1)

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "launch.hpp"
@@ -76,7 +77,7 @@ struct fdas_plan_s {
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   int64_t off_status = 0, off_tw[kNumFftSizes] = {}, off_exptab = 0, off_taps = 0, off_tspec = 0, off_desc = 0,
-          off_lists = 0, off_Y = 0, off_Zb = 0, off_spec = 0, total = 0;
+          off_lists = 0, off_Y = 0, off_Zb = 0, off_spec = 0, off_tw_conv = 0, total = 0;
   bool templates_ready = false;
   std::string err;
   // current batch
@@ -172,7 +173,8 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   if (p.r_lo < 0) return bad("r_lo must be >= 0");
   if (p.templates_per_tile < 0) return bad("templates_per_tile must be >= 0");
   if (p.interbin != 0 && p.interbin != 1) return bad("interbin must be 0 or 1");
-  if (p.reserved != 0) return bad("reserved must be 0");
+  const int radix = p.fft_radix ? p.fft_radix : 16;
+  if (!conv_radix_supported(L, radix)) return bad("fft_radix must be 0 or 16 (8 and 4 also at segment_len 1024)");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return bad("invalid device");
 
@@ -182,6 +184,7 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   pl->p.max_batch_samples = mb;
   pl->p.kernel_margin = margin;
   pl->p.segment_len = L;
+  pl->p.fft_radix = radix;
   pl->p.norm_block = B;
   pl->p.sigma_threshold = sig;
   pl->device = device;
@@ -218,6 +221,8 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
     pl->off_tw[i] = o;
     o = align256(o + (int64_t)twiddle_table_size(kFftSizes[i]) * (int64_t)sizeof(c32));
   }
+  pl->off_tw_conv = o;  // the convolution FFT's table when its radix is not 16
+  o = align256(o + (radix == 16 ? 0 : (int64_t)conv_twiddle_size(L, radix)) * (int64_t)sizeof(c32));
   pl->off_exptab = o;
   o = align256(o + (int64_t)L * 16);
   pl->off_taps = o;
@@ -282,6 +287,14 @@ fdas_status fdas_set_workspace(fdas_plan_t pl, void* dev_ptr, int64_t bytes) {
     e = hipStreamSynchronize(pl->stream);
     if (e != hipSuccess) return hip_fail(pl, e, "twiddle upload");
   }
+  if (pl->p.fft_radix != 16) {
+    const int n = conv_twiddle_size(pl->L, pl->p.fft_radix);
+    tab.assign(n, c32{0.f, 0.f});
+    conv_twiddle_fill(pl->L, pl->p.fft_radix, tab.data());
+    e = hipMemcpyAsync(pl->ws + pl->off_tw_conv, tab.data(), n * sizeof(c32), hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) return hip_fail(pl, e, "twiddle upload");
+  }
   e = hipMemsetAsync(pl->ws + pl->off_status, 0, 256, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "status clear");
   e = hipStreamSynchronize(pl->stream);
@@ -338,7 +351,8 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
     // W tile owners take tiles round-robin, so with T = nseg * G tiles the
     // launch lasts ceil(T/W) rounds of one tile (Z/G inverse FFTs plus the
     // segment's forward FFT): choose the G that minimises that product.
-    const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0));
+    const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.fft_radix, pl->p.store_dtype, pl->p.plane_dtype,
+                                                      pl->p.interbin != 0));
     const int64_t W = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
     double best = 1e300;
     G = 1;
@@ -462,6 +476,7 @@ static HarmArgs harm_args(fdas_plan_t pl, const void* plane, fdas_candidate* can
   a.hmax = pl->hmax * pl->res;
   a.res_shift = pl->res == 2 ? 1 : 0;
   a.max_bins = (int32_t)(pl->max_bins * pl->res);
+  a.series_base = 0;
   return a;
 }
 
@@ -477,7 +492,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   a.tspec = pl->ws + pl->off_tspec;
   a.plane = plane;
   a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
-  a.tw = pl->tw(pl->L);
+  a.tw = pl->p.fft_radix == 16 ? pl->tw(pl->L) : reinterpret_cast<const c32*>(pl->ws + pl->off_tw_conv);
   a.n_tiles = pl->n_tiles;
   a.n_series = (int)pl->desc.size();
   a.Z = pl->Z;
@@ -487,10 +502,12 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   // The grid is exactly what is resident at once: tiles are dealt
   // round-robin, so a block that had to wait for a slot would finish last.
   const int per_block = conv_waves_per_block(pl->L);
-  const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0));
+  const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.fft_radix, pl->p.store_dtype, pl->p.plane_dtype,
+                                                    pl->p.interbin != 0));
   const int64_t blocks_needed = pl->L == 1024 ? (pl->n_tiles + per_block - 1) / per_block : pl->n_tiles;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)pl->cu_count * per_cu));
-  hipError_t e = launch_conv(pl->L, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0, a, grid, pl->stream);
+  hipError_t e =
+      launch_conv(pl->L, pl->p.fft_radix, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0, a, grid, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "convolve");
   return FDAS_OK;
 }
@@ -625,6 +642,59 @@ fdas_status fdas_search(fdas_plan_t pl, const float* series, const int64_t* offs
   return FDAS_OK;
 }
 
+fdas_status fdas_search_chunked(fdas_plan_t pl, const float* series, const int64_t* offsets, const int64_t* lengths,
+                                int32_t n, void* plane, int64_t plane_bytes, fdas_candidate* cands, int64_t capacity,
+                                int64_t* d_count, int32_t* n_chunks) {
+  if (n_chunks) *n_chunks = 0;
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
+  if (!series || !offsets || !lengths || n <= 0 || !d_count || capacity < 0 || (capacity > 0 && !cands))
+    return pl->fail(FDAS_ERR_ARG, "series, offsets, lengths (n > 0) and d_count are required; cands when capacity > 0");
+  fdas_status s = check_harm_plane(pl, plane);
+  if (s != FDAS_OK) return s;
+  if (!plane) return pl->fail(FDAS_ERR_ARG, "plane is required");
+  // the chunks: longest runs of consecutive series whose samples fit
+  // max_batch_samples (and the per-call series limit) and whose plane fits
+  // plane_bytes; a series that fits neither alone is an error before any work
+  const int64_t N = pl->p.n_samples;
+  const int64_t per_bin = (int64_t)pl->Z * pl->res * rbytes(pl->p.plane_dtype);
+  std::vector<std::pair<int32_t, int32_t>> chunks;
+  for (int32_t i = 0; i < n;) {
+    int64_t samples = 0, bytes = 0;
+    int32_t j = i;
+    while (j < n) {
+      const int64_t len = lengths[j];
+      if (!(len == N || len == N / 2 || len == N / 4) || len < (1 << 17))
+        return pl->fail(FDAS_ERR_ARG, "series lengths must be n_samples, n_samples/2 or n_samples/4 (and >= 2^17)");
+      if (offsets[j] < 0 || (offsets[j] & 1)) return pl->fail(FDAS_ERR_ARG, "series offsets must be even and non-negative");
+      if (samples + len > pl->max_batch || bytes + len / 2 * per_bin > plane_bytes || j - i >= pl->max_series) break;
+      samples += len;
+      bytes += len / 2 * per_bin;
+      ++j;
+    }
+    if (j == i)
+      return pl->fail(FDAS_ERR_NOMEM, "plane_bytes is smaller than the plane of series " + std::to_string(i));
+    chunks.emplace_back(i, j - i);
+    i = j;
+  }
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  if ((e = launch_fill_i64(d_count, 1, 0, pl->stream)) != hipSuccess) return hip_fail(pl, e, "count reset");
+  void* spec = pl->ws + pl->off_spec;
+  for (const auto& c : chunks) {
+    // set_batch waits for the stream before it reuses its staging buffers
+    if ((s = set_batch(pl, offsets + c.first, lengths + c.first, c.second)) != FDAS_OK) return s;
+    if ((s = run_spectrum(pl, series, spec)) != FDAS_OK) return s;
+    if ((s = run_conv(pl, spec, plane, plane_bytes)) != FDAS_OK) return s;
+    HarmArgs a = harm_args(pl, plane, cands, capacity, d_count);
+    a.series_base = c.first;
+    if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, pl->stream)) != hipSuccess) return hip_fail(pl, e, "harmonic sum");
+  }
+  if (n_chunks) *n_chunks = (int32_t)chunks.size();
+  return FDAS_OK;
+}
+
 fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream, void* scratch, int64_t scratch_bytes,
                           fdas_params* best, double* best_ms) {
   if (!base || !best || !scratch) {
@@ -634,6 +704,7 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
   hipStream_t st = (hipStream_t)hip_stream;
   const int Ls[] = {1024, 2048, 4096, 8192};
   const int tpts[] = {0, 12, 24, 48, 96};
+  const int radices[] = {16, 8, 4};
   double best_t = 1e300;
   fdas_params winner = *base;
   bool any = false;
@@ -644,61 +715,67 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
     return FDAS_ERR_HIP;
   }
   fdas_status result = FDAS_OK;
-  for (int L : Ls) {
-    for (int tpt : tpts) {
-      fdas_params p = *base;
-      p.segment_len = L;
-      p.templates_per_tile = tpt;
-      p.max_batch_samples = p.n_samples;
-      fdas_plan_t pl = nullptr;
-      if (fdas_plan(&p, device, hip_stream, &pl) != FDAS_OK) continue;  // e.g. L < 4 h_max
-      if (tpt > pl->Z) {
-        fdas_plan_destroy(pl);
-        continue;
-      }
-      const int64_t nb = p.n_samples / 2;
-      const int64_t spec_bytes = align256(nb * cbytes(p.store_dtype));
-      const int64_t plane_bytes = align256(nb * pl->Z * pl->res * rbytes(p.plane_dtype));
-      const int64_t need = pl->total + spec_bytes + plane_bytes;
-      if (need > scratch_bytes) {
-        g_plan_error = "autotune scratch too small: need " + std::to_string(need) + " bytes";
-        fdas_plan_destroy(pl);
-        result = FDAS_ERR_NOMEM;
-        break;
-      }
-      char* base_ptr = (char*)scratch;
-      fdas_status s = fdas_set_workspace(pl, base_ptr, pl->total);
-      if (s == FDAS_OK) s = fdas_make_templates(pl);
-      void* spec = base_ptr + pl->total;
-      void* plane = base_ptr + pl->total + spec_bytes;
-      if (s == FDAS_OK && launch_fill_noise(spec, p.store_dtype, nb, 12345u, st) != hipSuccess) s = FDAS_ERR_HIP;
-      const int64_t len = p.n_samples;
-      float best_one = 1e30f;
-      for (int rep = 0; rep < 4 && s == FDAS_OK; ++rep) {
-        if (hipEventRecord(e0, st) != hipSuccess) {
-          s = FDAS_ERR_HIP;
-          break;
-        }
-        s = fdas_convolve_spectrum(pl, spec, &len, 1, plane, plane_bytes);
-        float ms = 0.f;
-        if (s == FDAS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          s = FDAS_ERR_HIP;
-        if (s == FDAS_OK && rep > 0) best_one = std::min(best_one, ms);  // first run warms up
-      }
-      if (s != FDAS_OK) g_plan_error = "autotune: " + (pl->err.empty() ? std::string("a HIP event call failed") : pl->err);
+  struct Cfg {
+    int L, tpt, radix;
+  };
+  std::vector<Cfg> cfgs;
+  for (int L : Ls)
+    for (int tpt : tpts)
+      for (int radix : radices)
+        if (conv_radix_supported(L, radix)) cfgs.push_back({L, tpt, radix});
+  for (const Cfg& c : cfgs) {
+    fdas_params p = *base;
+    p.segment_len = c.L;
+    p.templates_per_tile = c.tpt;
+    p.fft_radix = c.radix;
+    p.max_batch_samples = p.n_samples;
+    fdas_plan_t pl = nullptr;
+    if (fdas_plan(&p, device, hip_stream, &pl) != FDAS_OK) continue;  // e.g. L < 4 h_max
+    if (c.tpt > pl->Z) {
       fdas_plan_destroy(pl);
-      if (s != FDAS_OK) {
-        result = s;
+      continue;
+    }
+    const int64_t nb = p.n_samples / 2;
+    const int64_t spec_bytes = align256(nb * cbytes(p.store_dtype));
+    const int64_t plane_bytes = align256(nb * pl->Z * pl->res * rbytes(p.plane_dtype));
+    const int64_t need = pl->total + spec_bytes + plane_bytes;
+    if (need > scratch_bytes) {
+      g_plan_error = "autotune scratch too small: need " + std::to_string(need) + " bytes";
+      fdas_plan_destroy(pl);
+      result = FDAS_ERR_NOMEM;
+      break;
+    }
+    char* base_ptr = (char*)scratch;
+    fdas_status s = fdas_set_workspace(pl, base_ptr, pl->total);
+    if (s == FDAS_OK) s = fdas_make_templates(pl);
+    void* spec = base_ptr + pl->total;
+    void* plane = base_ptr + pl->total + spec_bytes;
+    if (s == FDAS_OK && launch_fill_noise(spec, p.store_dtype, nb, 12345u, st) != hipSuccess) s = FDAS_ERR_HIP;
+    const int64_t len = p.n_samples;
+    float best_one = 1e30f;
+    for (int rep = 0; rep < 4 && s == FDAS_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) {
+        s = FDAS_ERR_HIP;
         break;
       }
-      if (best_one < best_t) {
-        best_t = best_one;
-        winner = p;
-        any = true;
-      }
+      s = fdas_convolve_spectrum(pl, spec, &len, 1, plane, plane_bytes);
+      float ms = 0.f;
+      if (s == FDAS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        s = FDAS_ERR_HIP;
+      if (s == FDAS_OK && rep > 0) best_one = std::min(best_one, ms);  // first run warms up
     }
-    if (result != FDAS_OK) break;
+    if (s != FDAS_OK) g_plan_error = "autotune: " + (pl->err.empty() ? std::string("a HIP event call failed") : pl->err);
+    fdas_plan_destroy(pl);
+    if (s != FDAS_OK) {
+      result = s;
+      break;
+    }
+    if (best_one < best_t) {
+      best_t = best_one;
+      winner = p;
+      any = true;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -174,17 +174,20 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
 
 constexpr int kConvWaves = 4;  // wavefronts per block of the one-wavefront-per-FFT kernel
 
-// Convolution FFT shapes: 16 points per thread, radix 16 (the twiddle table
-// depends only on the radix sequence, so it is the one of ShapeOf<L>).
-template <int L>
-using ConvShape = FftShape<L, 16, 16>;
+// Convolution FFT shapes: 16 points per thread and passes of radix R (16 by
+// default; the 1024-point one-wavefront FFT is also built with R = 8, passes
+// 8 8 8 2, and R = 4, five passes of 4, for the autotuner).  The twiddle
+// table depends only on the radix sequence (conv_twiddle_size / _fill in
+// k_fft.hip).
+template <int L, int R = 16>
+using ConvShape = FftShape<L, 16, R>;
 
 // Two wavefronts per SIMD: with the template prefetch in registers a third
 // wavefront (possible for 16-bit storage) measured no faster.
-template <int L, int SDT, int PDT, bool IB>
+template <int L, int SDT, int PDT, bool IB, int R>
 __global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(2)))
 void k_conv_wave(ConvArgs a) {
-  using FS = ConvShape<L>;
+  using FS = ConvShape<L, R>;
   static_assert(FS::NT == 64, "one wavefront per FFT");
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[kConvWaves][FS::XBUF];
@@ -210,20 +213,22 @@ __global__ __launch_bounds__(ConvShape<L>::NT) __attribute__((amdgpu_waves_per_e
 
 int conv_waves_per_block(int L) { return L == 1024 ? kConvWaves : L / 16 / 64; }
 
-template <int L, int SDT, int PDT, bool IB>
+bool conv_radix_supported(int L, int R) { return R == 16 || (L == 1024 && (R == 8 || R == 4)); }
+
+template <int L, int SDT, int PDT, bool IB, int R>
 static void conv_launch(const ConvArgs& a, int grid, hipStream_t st) {
-  if constexpr (ConvShape<L>::NT == 64)
-    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT, IB>), dim3(grid), dim3(64 * kConvWaves), 0, st, a);
+  if constexpr (ConvShape<L, R>::NT == 64)
+    hipLaunchKernelGGL((k_conv_wave<L, SDT, PDT, IB, R>), dim3(grid), dim3(64 * kConvWaves), 0, st, a);
   else
     hipLaunchKernelGGL((k_conv_block<L, SDT, PDT, IB>), dim3(grid), dim3(ConvShape<L>::NT), 0, st, a);
 }
 
-template <int L, int SDT, int PDT, bool IB>
+template <int L, int SDT, int PDT, bool IB, int R>
 static int occ() {
   int n = 0;
   hipError_t e;
-  if constexpr (ConvShape<L>::NT == 64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT, IB>, 64 * kConvWaves, 0);
+  if constexpr (ConvShape<L, R>::NT == 64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_wave<L, SDT, PDT, IB, R>, 64 * kConvWaves, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_conv_block<L, SDT, PDT, IB>, ConvShape<L>::NT, 0);
   if (e != hipSuccess) n = 1;
@@ -240,36 +245,54 @@ static auto with_dtype(int dt, F&& f) {
   }
 }
 
+// Calls f(integral_constant<int, R>) for the radices built at length L.
+template <int L, class F>
+static auto with_radix(int r, F&& f) {
+  if constexpr (L == 1024) {
+    if (r == 8) return f(std::integral_constant<int, 8>{});
+    if (r == 4) return f(std::integral_constant<int, 4>{});
+  }
+  return f(std::integral_constant<int, 16>{});
+}
+
 template <int L>
-static int occ_l(int sdt, int pdt, bool ib) {
-  return with_dtype(sdt, [&](auto sd) {
-    return with_dtype(pdt, [&](auto pd) {
-      constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
-      return ib ? occ<L, S, Q, true>() : occ<L, S, Q, false>();
+static int occ_l(int r, int sdt, int pdt, bool ib) {
+  return with_radix<L>(r, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    return with_dtype(sdt, [&](auto sd) {
+      return with_dtype(pdt, [&](auto pd) {
+        constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
+        return ib ? occ<L, S, Q, true, R>() : occ<L, S, Q, false, R>();
+      });
     });
   });
 }
 
-int conv_blocks_per_cu(int L, int sdt, int pdt, bool interbin) {
+int conv_blocks_per_cu(int L, int R, int sdt, int pdt, bool interbin) {
   switch (L) {
-    case 1024: return occ_l<1024>(sdt, pdt, interbin);
-    case 2048: return occ_l<2048>(sdt, pdt, interbin);
-    case 4096: return occ_l<4096>(sdt, pdt, interbin);
-    case 8192: return occ_l<8192>(sdt, pdt, interbin);
+    case 1024: return occ_l<1024>(R, sdt, pdt, interbin);
+    case 2048: return occ_l<2048>(R, sdt, pdt, interbin);
+    case 4096: return occ_l<4096>(R, sdt, pdt, interbin);
+    case 8192: return occ_l<8192>(R, sdt, pdt, interbin);
     default: return 1;
   }
 }
 
 template <int L>
-static hipError_t conv_l(int sdt, int pdt, bool ib, const ConvArgs& a, int grid, hipStream_t st) {
+static hipError_t conv_l(int r, int sdt, int pdt, bool ib, const ConvArgs& a, int grid, hipStream_t st) {
   if (sdt < FDAS_F32 || sdt > FDAS_F16 || pdt < FDAS_F32 || pdt > FDAS_F16) return hipErrorInvalidValue;
-  with_dtype(sdt, [&](auto sd) {
-    with_dtype(pdt, [&](auto pd) {
-      constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
-      if (ib)
-        conv_launch<L, S, Q, true>(a, grid, st);
-      else
-        conv_launch<L, S, Q, false>(a, grid, st);
+  if (!conv_radix_supported(L, r)) return hipErrorInvalidValue;
+  with_radix<L>(r, [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    with_dtype(sdt, [&](auto sd) {
+      with_dtype(pdt, [&](auto pd) {
+        constexpr int S = decltype(sd)::value, Q = decltype(pd)::value;
+        if (ib)
+          conv_launch<L, S, Q, true, R>(a, grid, st);
+        else
+          conv_launch<L, S, Q, false, R>(a, grid, st);
+        return 0;
+      });
       return 0;
     });
     return 0;
@@ -277,12 +300,12 @@ static hipError_t conv_l(int sdt, int pdt, bool ib, const ConvArgs& a, int grid,
   return hipGetLastError();
 }
 
-hipError_t launch_conv(int L, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st) {
+hipError_t launch_conv(int L, int R, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st) {
   switch (L) {
-    case 1024: return conv_l<1024>(sdt, pdt, interbin, a, grid, st);
-    case 2048: return conv_l<2048>(sdt, pdt, interbin, a, grid, st);
-    case 4096: return conv_l<4096>(sdt, pdt, interbin, a, grid, st);
-    case 8192: return conv_l<8192>(sdt, pdt, interbin, a, grid, st);
+    case 1024: return conv_l<1024>(R, sdt, pdt, interbin, a, grid, st);
+    case 2048: return conv_l<2048>(R, sdt, pdt, interbin, a, grid, st);
+    case 4096: return conv_l<4096>(R, sdt, pdt, interbin, a, grid, st);
+    case 8192: return conv_l<8192>(R, sdt, pdt, interbin, a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -55,6 +55,21 @@ void twiddle_table_fill(int L, c32* dst) {
   }
 }
 
+// Tables of the convolution's FFT shapes: 16 points per thread, passes of
+// radix R (the radix-16 ones are the tables above).
+int conv_twiddle_size(int L, int R) {
+  if (R == 16) return twiddle_table_size(L);
+  if (L == 1024 && R == 8) return FftShape<1024, 16, 8>::TW_SIZE;
+  if (L == 1024 && R == 4) return FftShape<1024, 16, 4>::TW_SIZE;
+  return 0;
+}
+
+void conv_twiddle_fill(int L, int R, c32* dst) {
+  if (R == 16) twiddle_table_fill(L, dst);
+  else if (L == 1024 && R == 8) fill_table<FftShape<1024, 16, 8>>(dst);
+  else if (L == 1024 && R == 4) fill_table<FftShape<1024, 16, 4>>(dst);
+}
+
 // One FFT per group of NT threads; blocks hold whole groups.
 template <int L, int DIR>
 __global__ __launch_bounds__(512) void k_test_fft(const c32* __restrict__ in, c32* __restrict__ out, int64_t batch,

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     if ((int64_t)slot < a.capacity) {
       const int hh = 1 << bi;
       fdas_candidate c;
-      c.series = (int)blockIdx.z;
+      c.series = (int)blockIdx.z + a.series_base;
       c.harm = hh;
       c.R = R;
       c.j = j;

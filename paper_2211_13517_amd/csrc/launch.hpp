@@ -67,9 +67,13 @@ struct ConvArgs {
   int32_t n_series, Z, G, U, hmax;
 };
 // interbin: also write the half-bin power between each output and the next
-hipError_t launch_conv(int L, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st);
+// R: radix of the convolution FFT's passes (16; 8 or 4 at L = 1024)
+hipError_t launch_conv(int L, int R, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st);
 int conv_waves_per_block(int L);
-int conv_blocks_per_cu(int L, int sdt, int pdt, bool interbin);  // resident blocks per CU (occupancy query)
+int conv_blocks_per_cu(int L, int R, int sdt, int pdt, bool interbin);  // resident blocks per CU (occupancy query)
+bool conv_radix_supported(int L, int R);
+int conv_twiddle_size(int L, int R);           // entries of the convolution FFT's twiddle table
+void conv_twiddle_fill(int L, int R, c32* dst);
 
 // harmonic sums
 struct HarmArgs {
@@ -85,7 +89,8 @@ struct HarmArgs {
   // columns
   int32_t n_series, Z, j0, n_harm, r_lo, hmax;
   int32_t res_shift;
-  int32_t max_bins;  // longest series in the batch (sets the tile grid)
+  int32_t max_bins;     // longest series in the batch (sets the tile grid)
+  int32_t series_base;  // added to the batch index in the records' series field
 };
 hipError_t launch_harmonic_sum(int pdt, const HarmArgs& a, hipStream_t st);
 

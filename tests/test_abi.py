@@ -65,7 +65,8 @@ BAD = [
     dict(sigma_threshold=-1.0),
     dict(max_batch_samples=1 << 10),
     dict(interbin=2),
-    dict(reserved=1),
+    dict(fft_radix=3),
+    dict(fft_radix=8, segment_len=2048),
 ]
 
 

@@ -180,6 +180,27 @@ def test_plane_fp32_small_case_full_parity(lib, L):
     assert abs(r - 5010) <= 2 and zs[j] >= 12
 
 
+@pytest.mark.parametrize("radix,interbin", [(8, 0), (4, 0), (8, 1), (4, 1)])
+def test_plane_radix_plans_match_oracle(lib, radix, interbin):
+    """The 1024-point convolution FFT built with passes of radix 8 (8 8 8 2)
+    and 4 (five passes), the autotuner's other radix plans: every cell of the
+    small case's FP32 plane (bin or half-bin) within 1e-4 max(P, 1) of the
+    oracle's."""
+    x, inj, _ = synth.small_case(seed=1)
+    say("fdas_convolve radix plan", radix, "interbin" if interbin else "bins")
+    n = len(x)
+    pl = lib.Plan(store="f32", plane="f32", n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, n_harmonics=4,
+                  segment_len=1024, fft_radix=radix, interbin=interbin)
+    import torch
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
+    zs = o.z_grid(-16, 16, 2)
+    a = o.normalise(o.spectrum(x), "median")
+    ref = o.interbin_plane(a, zs) if interbin else o.power_plane(a, zs)
+    got = P.cpu().numpy().astype(np.float64).reshape(pl.Z, -1)
+    bad = np.abs(got - ref) > 1e-4 * np.maximum(ref, 1.0)
+    assert not bad.any(), (np.argwhere(bad)[:5], np.abs(got - ref).max())
+
+
 @pytest.mark.parametrize("store,plane", [("bf16", "bf16"), ("bf16", "f32"), ("f16", "f16")])
 def test_plane_reduced_precision_small_case(lib, store, plane):
     x, inj, _ = synth.small_case(seed=1)
@@ -755,6 +776,7 @@ def test_autotune_picks_a_valid_configuration(lib, interbin):
                         store="bf16", plane="bf16", interbin=interbin)
     assert best.interbin == interbin
     assert best.segment_len in (1024, 2048, 4096, 8192)
+    assert best.fft_radix in ((16, 8, 4) if best.segment_len == 1024 else (16,))
     x = synth.make_series(n, [synth.Injection(0.05, 7000.0, 21.0, 0.3)], 52, 0)
     pl = lib.Plan(params=best, n_samples=n)
     P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
@@ -763,3 +785,44 @@ def test_autotune_picks_a_valid_configuration(lib, interbin):
     got = P.view(pl.Z, n // 2 * pl.res).float().cpu().numpy()[[0, 25, 32, 53, 64]][:, ::pl.res]
     e = o.power_errors(got, ref, tau1=o.threshold(1))
     assert e["max_rel_det"] < 3e-2
+
+
+def test_search_chunked_equals_one_search(lib):
+    """fdas_search_chunked over 6 series of the three length classes with a
+    plane buffer that holds about two of them: several chunks, and exactly
+    the records (global series indices) of one fdas_search over all six with
+    a plane for all; a buffer smaller than one series' plane is refused
+    before any work."""
+    import ctypes
+    import torch
+    n = 1 << 19
+    lens = [n, n // 2, n // 4, n, n // 2, n]
+    xs, _ = synth.batch_series(lens, seed=85, inj_per_series=(1, 2), amp=(0.05, 0.08), z_abs=28.0)
+    flat, offs, lens_a = synth.concat(xs)
+    say("fdas_search_chunked", lens)
+    pl = lib.Plan(n_samples=n, max_batch_samples=int(lens_a.sum()), z_min=-32.0, z_max=32.0, z_step=2.0,
+                  n_harmonics=8, segment_len=1024, store="bf16", plane="bf16")
+    xt = torch.from_numpy(flat).to("cuda")
+    cap = 1 << 20
+    P_all = pl.new_plane(int(lens_a.sum()) // 2)
+    c0 = torch.zeros((cap, 8), dtype=torch.int32, device="cuda")
+    k0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pl.search(xt, offs, lens_a, P_all, c0, k0)
+    pl.check(k0, cap)
+    want = np.sort(lib.candidates_to_numpy(c0, int(k0.item())), order=["series", "j", "R"])
+    P_small = pl.new_plane(2 * n // 2)   # the plane of two full-length series
+    c1 = torch.zeros_like(c0)
+    k1 = torch.full((1,), 99, dtype=torch.int64, device="cuda")
+    nch = pl.search_chunked(xt, offs, lens_a, P_small, c1, k1)
+    pl.check(k1, cap)
+    got = np.sort(lib.candidates_to_numpy(c1, int(k1.item())), order=["series", "j", "R"])
+    assert nch >= 3, nch
+    assert len(want) > 50 and np.array_equal(got, want)
+    assert set(got["series"].tolist()) == set(range(len(lens)))
+    # too small for the longest series: refused, nothing enqueued
+    tiny = pl.new_plane(n // 4)
+    k2 = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    with pytest.raises(lib.FdasError, match="plane_bytes"):
+        pl.search_chunked(xt, offs, lens_a, tiny, c1, k2)
+    torch.cuda.synchronize()
+    assert int(k2.item()) == 7
