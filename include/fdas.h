@@ -40,6 +40,18 @@
  *    order, series i starting at complex element S_i = sum_{k<i} N_k/2.  Power
  *    planes are packed the same way, series i starting at element Z*S_i and
  *    laid out z-major: plane_i[j][r], j < Z acceleration trials, r < N_i/2.
+ *  - Plane buffers: the packed plane values (C = sum_i N_i/2 columns per
+ *    trial, twice that on a half-bin plane; Z*C elements of plane_dtype) are
+ *    followed by their column maxima, Z*C/8 elements of plane_dtype: series
+ *    i's from element Z*S_i/8 of that section (Z*S_i/4 on a half-bin plane),
+ *    row j holding M_i[j][c] = max_{q<8} plane_i[j][8c + q], a NaN or
+ *    negative value (sign bit set) counting as +inf, so that M bounds every
+ *    value of its run whatever they are.  A plane buffer therefore holds
+ *    9*Z*C/8 elements.  The convolution writes both parts; the harmonic sum
+ *    reads both (it bounds the upper half of the harmonics by the maxima and
+ *    sums exactly only where a bound passes, see fdas_harmonic_sum).  A
+ *    caller that writes plane values itself calls fdas_plane_maxima before
+ *    the harmonic sum.
  */
 #ifndef FDAS_H
 #define FDAS_H
@@ -98,12 +110,13 @@ typedef struct {
  *  - the plane of series i has 2 N_i/2 = N_i columns per trial and starts at
  *    element 2 Z S_i; column 2r holds P[j][r], column 2r+1 the half-bin power
  *    between r and r+1 (y(N_i/2) from the zero-extended spectrum);
- *  - U = L - 2 h_max - 1, so every segment holds y at its last output + 1;
+ *  - U <= L - 2 h' - 1 (fdas_plan), so every segment holds y at its last
+ *    output + 1;
  *  - fdas_harmonic_sum works on half-bin columns: R counts half bins, a cell
  *    is searched at stage H' if R >= 2 H' r_lo and R < 2 (N/2 - h_max), and
  *    the record's r = R / (2H) bins;
  *  - fdas_cluster's radius_r counts half bins;
- *  - plane buffers must be aligned to two plane elements (8 bytes for F32). */
+ *  - plane buffers are 16-byte aligned (as every plane buffer). */
 
 /* One detection: 32 bytes. harm is the number of harmonics summed (H), R and j
  * the cell of the H-th harmonic (bin, or half bin on a half-bin plane;
@@ -126,8 +139,10 @@ fdas_status fdas_default_params(fdas_params *p);
  * takes, searched over 193 acceleration trials).
  * Validates *params and creates a plan bound to `device` and the HIP stream
  * `hip_stream` (NULL = default stream).  Derived sizes: Z = (z_max - z_min)/z_step + 1,
- * h_max = ceil(z_max/2) + m, U = L - 2 h_max outputs per segment (one fewer on
- * a half-bin plane).  Thresholds
+ * h_max = ceil(z_max/2) + m; segments keep U outputs from FFT index h',
+ * h' = h_max rounded up to a multiple of 8 (of 4 on a half-bin plane) and U
+ * the largest such multiple <= L - 2 h' (<= L - 2 h' - 1 on a half-bin
+ * plane), so that every run of 8 plane columns lies in one segment.  Thresholds
  * tau_H solve P(Gamma(H,1) > tau_H) = P(N(0,1) > sigma_threshold) in FP64: a
  * noise harmonic sum of H unit-mean exponential powers is Gamma(H,1).
  * On failure *out is NULL and the message is available from fdas_last_error(NULL). */
@@ -169,13 +184,15 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
  * frequency domain through FFTs, this stage's data stored in store_dtype and
  * its arithmetic in FP32; section 2.1: one output row per acceleration trial).
  * From a normalised spectrum (store_dtype, packed): overlap-save
- * segments of L bins starting at s U - h_max (zero outside [0, N/2)), one
- * forward FFT per segment, then for every template j: product with T_j,
- * inverse FFT, and P[j][s U + i] = |y[h_max + i]|^2 for i < U, i.e.
+ * segments of L bins starting at s U - h' (zero outside [0, N/2); h' and U
+ * as at fdas_plan), one forward FFT per segment, then for every template j:
+ * product with T_j, inverse FFT, and P[j][s U + i] = |y[h' + i]|^2 for
+ * i < U, i.e.
  *   P[j][r] = | sum_{q=-h_max}^{h_max} A'_{r+q} t_q(z_j) |^2,
  * written to plane_out (plane_dtype, packed z-major; with interbin the
- * half-bin plane described at fdas_params).  plane_bytes is the size of
- * plane_out and must cover the whole batch. */
+ * half-bin plane described at fdas_params), together with the column
+ * maxima of the plane-buffer convention.  plane_bytes is the size of
+ * plane_out and must cover the whole batch (9*Z*C/8 elements). */
 fdas_status fdas_convolve_spectrum(fdas_plan_t plan, const void *spectrum, const int64_t *lengths_host,
                                    int32_t n_series, void *plane_out, int64_t plane_bytes);
 
@@ -186,11 +203,21 @@ fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out,
                           void *plane_out, int64_t plane_bytes);
 
+/* Column maxima of a plane buffer whose values the caller wrote (an
+ * addition: the harmonic sum's bound, see the plane-buffer convention above;
+ * the convolution entry points write them with the plane).  plane: device,
+ * 16-byte aligned; plane_bytes: its size, at least 9*Z*C/8 elements of
+ * plane_dtype for the batch given by lengths_host (FDAS_ERR_NOMEM otherwise).
+ * Reads the values, writes the maxima section. */
+fdas_status fdas_plane_maxima(fdas_plan_t plan, void *plane, const int64_t *lengths_host, int32_t n_series,
+                              int64_t plane_bytes);
+
 /* Harmonic sums (the introduction's harmonic-summing stage, which follows the
  * correlation; the paper names it without formulas, so the index rule below
  * is this library's reading): nested harmonic sums and thresholding over a
- * packed plane.  plane: device, 16-byte aligned (FDAS_ERR_ARG otherwise).
- * For cell (R, j) with m = j - j0 (j0 the z = 0 trial) and H the top stage,
+ * plane buffer (values and column maxima, as fdas_convolve* or
+ * fdas_plane_maxima left it).  plane: device, 16-byte aligned (FDAS_ERR_ARG
+ * otherwise).  For cell (R, j) with m = j - j0 (j0 the z = 0 trial) and H the top stage,
  *   S_H(R, j) = sum_{k=1}^{H} P[j0 + sgn(m) floor((2k|m| + H)/(2H))][floor((2kR + H)/(2H))],
  * and the lower stages H' use the terms k = H/H', 2H/H', ..., H.  A cell is
  * searched at stage H' if R >= H' r_lo and R < N/2 - h_max, passes if
@@ -199,7 +226,11 @@ fdas_status fdas_convolve(fdas_plan_t plan, const float *series, const int64_t *
  * (device, `capacity` records, order not deterministic); *d_count (device
  * int64, zeroed by the caller before the first call of a search) counts every
  * passing cell, also those that did not fit.  On a half-bin plane the same
- * sums run over half-bin columns (see fdas_params). */
+ * sums run over half-bin columns (see fdas_params).  The sums are first
+ * bounded with each term k > H/2 replaced by the column maximum over its
+ * run of 8 columns; only cells with a bound at or above a threshold read
+ * those terms from the plane and sum exactly, in the same order, so the
+ * records are those of the exact sums (stale maxima would lose detections). */
 fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t *lengths_host,
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);
@@ -280,8 +311,9 @@ fdas_status fdas_search(fdas_plan_t plan, const float *series, const int64_t *of
 
 /* The whole search for a batch of any size within a plane buffer of
  * plane_bytes (the HBM budget): the series are taken in consecutive chunks,
- * each the longest run whose samples fit max_batch_samples and whose planes
- * fit plane_bytes, and every chunk runs as fdas_search (spectrum in the
+ * each the longest run whose samples fit max_batch_samples and whose plane
+ * buffers (values and maxima) fit plane_bytes, and every chunk runs as
+ * fdas_search (spectrum in the
  * workspace; no graph).  *d_count is reset once (with a kernel) and counts
  * the passing cells of every chunk; the records' series field is the index
  * in offsets/lengths.  The planes are overwritten chunk by chunk (the last
@@ -297,8 +329,8 @@ fdas_status fdas_search_chunked(fdas_plan_t plan, const float *series, const int
  * for every segment length L in {1024, 2048, 4096, 8192} allowed by the z
  * range, templates_per_tile in {auto, 12, 24, 48, 96} and FFT radix plan
  * (fft_radix 16, and 8 and 4 at L = 1024) on `device`/`hip_stream`,
- * using `scratch` (device memory, at least workspace + spectrum + plane of one
- * series; FDAS_ERR_NOMEM names the size), and writes the fastest parameters
+ * using `scratch` (device memory, at least workspace + spectrum + plane
+ * buffer of one series; FDAS_ERR_NOMEM names the size), and writes the fastest parameters
  * to *best (and its time in ms to *best_ms).  Blocks until done. */
 fdas_status fdas_autotune(const fdas_params *base, int device, void *hip_stream, void *scratch,
                           int64_t scratch_bytes, fdas_params *best, double *best_ms);

@@ -53,9 +53,15 @@ EXPORTS = ["fdas_default_params", "fdas_plan", "fdas_query", "fdas_set_workspace
            "fdas_rz_power", "fdas_rz_power_grad", "fdas_refine", "fdas_search", "fdas_autotune",
            "fdas_copy_templates", "fdas_copy_thresholds", "fdas_test_fft", "fdas_plan_destroy",
            "fdas_last_error", "fdas_cluster_scratch_bytes", "fdas_cluster", "fdas_refine_harmonics",
-           "fdas_cluster_noalloc", "fdas_search_chunked"]
+           "fdas_cluster_noalloc", "fdas_search_chunked", "fdas_plane_maxima"]
 
 _lib = None
+
+
+def _buffer_bytes(t) -> int:
+    """Bytes from a tensor's first element to the end of its allocation: a
+    plane buffer's values view also reaches the column maxima after them."""
+    return t.untyped_storage().nbytes() - t.storage_offset() * t.element_size()
 
 
 def load(path: str = LIB_PATH):
@@ -78,6 +84,7 @@ def load(path: str = LIB_PATH):
         "fdas_convolve_spectrum": ([P, P, POINTER(c_int64), c_int32, P, c_int64], c_int),
         "fdas_convolve": ([P, P, POINTER(c_int64), POINTER(c_int64), c_int32, P, P, c_int64], c_int),
         "fdas_harmonic_sum": ([P, P, POINTER(c_int64), c_int32, P, c_int64, P], c_int),
+        "fdas_plane_maxima": ([P, P, POINTER(c_int64), c_int32, c_int64], c_int),
         "fdas_check": ([P, P, c_int64], c_int),
         "fdas_rz_power": ([P, P, c_int64, P, P, c_int64, P, P], c_int),
         "fdas_rz_power_grad": ([P, P, c_int64, P, P, P, P, c_int64, P, P, P], c_int),
@@ -214,9 +221,24 @@ class Plan:
         return torch.empty((total_bins, 2), dtype=spectrum_torch_dtype(self.store_dtype), device=self.device)
 
     def new_plane(self, total_bins: int):
+        """A plane buffer for ``total_bins`` bins in all: returns the view of
+        its Z * total_bins * res plane values; the column maxima (one eighth
+        more) follow them in the same allocation (see ``maxima``)."""
         import torch
-        return torch.empty(self.Z * total_bins * self.res, dtype=plane_torch_dtype(self.plane_dtype),
-                           device=self.device)
+        n = self.Z * total_bins * self.res
+        buf = torch.empty(n + n // 8, dtype=plane_torch_dtype(self.plane_dtype), device=self.device)
+        return buf[:n]
+
+    @staticmethod
+    def maxima(plane):
+        """The column-maxima section that follows a plane made by ``new_plane``."""
+        return plane._base[plane.numel():]
+
+    def plane_maxima(self, plane, lengths: Sequence[int]):
+        """Writes the column maxima of plane values the caller wrote (fdas_plane_maxima)."""
+        self._check(self.lib.fdas_plane_maxima(self.handle, c_void_p(plane.data_ptr()), _i64(lengths), len(lengths),
+                                               _buffer_bytes(plane)))
+        return plane
 
     def spectrum(self, series, offsets: Sequence[int], lengths: Sequence[int], out=None):
         total = int(sum(lengths)) // 2
@@ -228,7 +250,7 @@ class Plan:
     def convolve_spectrum(self, spectrum, lengths: Sequence[int], plane=None):
         total = int(sum(lengths)) // 2
         plane = self.new_plane(total) if plane is None else plane
-        nbytes = plane.numel() * plane.element_size()
+        nbytes = _buffer_bytes(plane)
         self._check(self.lib.fdas_convolve_spectrum(self.handle, c_void_p(spectrum.data_ptr()), _i64(lengths),
                                                     len(lengths), c_void_p(plane.data_ptr()), nbytes))
         return plane
@@ -236,7 +258,7 @@ class Plan:
     def convolve(self, series, offsets: Sequence[int], lengths: Sequence[int], plane=None, spectrum=None):
         total = int(sum(lengths)) // 2
         plane = self.new_plane(total) if plane is None else plane
-        nbytes = plane.numel() * plane.element_size()
+        nbytes = _buffer_bytes(plane)
         sp = None if spectrum is None else c_void_p(spectrum.data_ptr())
         self._check(self.lib.fdas_convolve(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
                                            len(lengths), sp, c_void_p(plane.data_ptr()), nbytes))
@@ -256,7 +278,7 @@ class Plan:
     def search(self, series, offsets: Sequence[int], lengths: Sequence[int], plane, cands, count,
                spectrum=None, use_graph: bool = False):
         """The whole search, spectrum to candidates, for one batch (optionally through a captured HIP graph)."""
-        nbytes = plane.numel() * plane.element_size()
+        nbytes = _buffer_bytes(plane)
         self._check(self.lib.fdas_search(self.handle, c_void_p(series.data_ptr()), _i64(offsets), _i64(lengths),
                                          len(lengths), None if spectrum is None else c_void_p(spectrum.data_ptr()),
                                          c_void_p(plane.data_ptr()), nbytes, c_void_p(cands.data_ptr()),
@@ -265,7 +287,7 @@ class Plan:
     def search_chunked(self, series, offsets: Sequence[int], lengths: Sequence[int], plane, cands, count) -> int:
         """The whole search over any number of series within ``plane``'s size
         (fdas_search_chunked); returns the number of chunks."""
-        nbytes = plane.numel() * plane.element_size()
+        nbytes = _buffer_bytes(plane)
         nch = c_int32()
         self._check(self.lib.fdas_search_chunked(self.handle, c_void_p(series.data_ptr()), _i64(offsets),
                                                  _i64(lengths), len(lengths), c_void_p(plane.data_ptr()), nbytes,
@@ -408,7 +430,7 @@ def autotune(device: int = 0, stream=None, cache: Optional[str] = None, **kw) ->
     st = stream if stream is not None else torch.cuda.current_stream(device)
     nb = p.n_samples // 2
     z = int(round((p.z_max - p.z_min) / p.z_step)) + 1
-    need = nb * 8 + nb * z * 4 + nb * 40 + (64 << 20)
+    need = nb * 8 + nb * z * 4 * (2 if p.interbin else 1) * 9 // 8 + nb * 40 + (64 << 20)
     scratch = torch.empty(need, dtype=torch.uint8, device=f"cuda:{device}")
     best, ms = Params(), c_double()
     st_ = lib.fdas_autotune(byref(p), device, c_void_p(st.cuda_stream), c_void_p(scratch.data_ptr()), need,

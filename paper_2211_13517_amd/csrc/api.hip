@@ -67,7 +67,7 @@ struct fdas_plan_s {
   fdas_params p{};
   int device = 0;
   hipStream_t stream = nullptr;
-  int Z = 0, j0 = 0, hmax = 0, K = 0, L = 0, U = 0, nstages = 0;
+  int Z = 0, j0 = 0, hmax = 0, K = 0, L = 0, U = 0, seg_margin = 0, nstages = 0;
   int res = 1;  // plane columns per bin: 2 on a half-bin plane
   double tau[5] = {0, 0, 0, 0, 0};
   int64_t max_batch = 0;
@@ -196,7 +196,14 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   pl->L = L;
   // a half-bin plane needs y one past the last output of each segment
   pl->res = p.interbin ? 2 : 1;
-  pl->U = L - 2 * hmax - (p.interbin ? 1 : 0);
+  // Segments put their first output seg_margin >= h_max points into the
+  // FFT and keep U outputs, both multiples of the bins per column maximum,
+  // so every run of 8 plane columns lies in one segment and the convolution
+  // writes its maximum (a half-bin plane needs y one past each segment's
+  // last output as well).
+  const int run = kPlaneMaxCols / pl->res;
+  pl->seg_margin = (hmax + run - 1) / run * run;
+  pl->U = (L - 2 * pl->seg_margin - (p.interbin ? 1 : 0)) / run * run;
   pl->nstages = log2i(p.n_harmonics) + 1;
   if (pl->p.r_lo == 0) pl->p.r_lo = hmax;
   for (int i = 0; i < pl->nstages; ++i) pl->tau[i] = threshold_for(1 << i, sig);
@@ -452,8 +459,18 @@ static fdas_status check_harm_plane(fdas_plan_t pl, const void* plane) {
   return FDAS_OK;
 }
 
-// Bytes of the packed planes of the current batch.
-static int64_t plane_need(fdas_plan_t pl) { return pl->total_bins * pl->Z * pl->res * rbytes(pl->p.plane_dtype); }
+// Bytes of the packed plane values of `bins` bins in all, and of a plane
+// buffer for them: the values, then their column maxima.
+static int64_t plane_data_bytes(fdas_plan_t pl, int64_t bins) {
+  return bins * pl->Z * pl->res * rbytes(pl->p.plane_dtype);
+}
+static int64_t plane_buffer_bytes(fdas_plan_t pl, int64_t bins) {
+  return plane_data_bytes(pl, bins) + plane_data_bytes(pl, bins) / kPlaneMaxCols;
+}
+static int64_t plane_need(fdas_plan_t pl) { return plane_buffer_bytes(pl, pl->total_bins); }
+static void* plane_maxima(fdas_plan_t pl, const void* plane) {
+  return const_cast<char*>(reinterpret_cast<const char*>(plane)) + plane_data_bytes(pl, pl->total_bins);
+}
 
 // Harmonic-sum arguments for the current batch; on a half-bin plane the bin
 // limits are given in half bins.
@@ -461,6 +478,7 @@ static HarmArgs harm_args(fdas_plan_t pl, const void* plane, fdas_candidate* can
                           int64_t* d_count) {
   HarmArgs a;
   a.plane = plane;
+  a.maxima = plane_maxima(pl, plane);
   a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
   a.cands = cands;
   a.count = reinterpret_cast<unsigned long long*>(d_count);
@@ -484,13 +502,13 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   if (!pl->templates_ready) return pl->fail(FDAS_ERR_STATE, "fdas_make_templates has not run");
   const int64_t need = plane_need(pl);
   if (!plane || plane_bytes < need) return pl->fail(FDAS_ERR_NOMEM, "plane buffer missing or too small");
-  // a half-bin plane is written as (bin, half-bin) pairs
-  if (((uintptr_t)plane) % (uintptr_t)(rbytes(pl->p.plane_dtype) * pl->res))
-    return pl->fail(FDAS_ERR_ARG, "plane must be aligned to its element size (twice that on a half-bin plane)");
+  // (bin, half-bin) pairs are written as one store, the maxima read in 16-byte pieces
+  if (((uintptr_t)plane) & 15) return pl->fail(FDAS_ERR_ARG, "plane buffers must be 16-byte aligned");
   ConvArgs a;
   a.spec = spec;
   a.tspec = pl->ws + pl->off_tspec;
   a.plane = plane;
+  a.maxima = plane_maxima(pl, plane);
   a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);
   a.tw = pl->p.fft_radix == 16 ? pl->tw(pl->L) : reinterpret_cast<const c32*>(pl->ws + pl->off_tw_conv);
   a.n_tiles = pl->n_tiles;
@@ -498,7 +516,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   a.Z = pl->Z;
   a.G = pl->G;
   a.U = pl->U;
-  a.hmax = pl->hmax;
+  a.seg_margin = pl->seg_margin;
   // The grid is exactly what is resident at once: tiles are dealt
   // round-robin, so a block that had to wait for a slot would finish last.
   const int per_block = conv_waves_per_block(pl->L);
@@ -552,6 +570,23 @@ fdas_status fdas_convolve(fdas_plan_t pl, const float* series, const int64_t* of
   void* spec = spec_out ? spec_out : (void*)(pl->ws + pl->off_spec);
   if ((s = run_spectrum(pl, series, spec)) != FDAS_OK) return s;
   return run_conv(pl, spec, plane, plane_bytes);
+}
+
+fdas_status fdas_plane_maxima(fdas_plan_t pl, void* plane, const int64_t* lengths, int32_t n, int64_t plane_bytes) {
+  if (!pl) return FDAS_ERR_ARG;
+  if (!pl->ws) return pl->fail(FDAS_ERR_STATE, "no workspace bound");
+  if (!plane) return pl->fail(FDAS_ERR_ARG, "plane is required");
+  if (((uintptr_t)plane) & 15) return pl->fail(FDAS_ERR_ARG, "plane must be 16-byte aligned");
+  hipError_t e = hipSetDevice(pl->device);
+  if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
+  fdas_status s = ensure_lengths(pl, lengths, n);
+  if (s != FDAS_OK) return s;
+  if (plane_bytes < plane_need(pl)) return pl->fail(FDAS_ERR_NOMEM, "plane buffer too small for the values and their maxima");
+  e = launch_plane_maxima(pl->p.plane_dtype, plane, plane_maxima(pl, plane),
+                          reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc), (int)pl->desc.size(), pl->Z,
+                          pl->res == 2 ? 1 : 0, pl->max_bins, pl->cu_count, pl->stream);
+  if (e != hipSuccess) return hip_fail(pl, e, "column maxima");
+  return FDAS_OK;
 }
 
 fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* lengths, int32_t n,
@@ -658,7 +693,7 @@ fdas_status fdas_search_chunked(fdas_plan_t pl, const float* series, const int64
   // max_batch_samples (and the per-call series limit) and whose plane fits
   // plane_bytes; a series that fits neither alone is an error before any work
   const int64_t N = pl->p.n_samples;
-  const int64_t per_bin = (int64_t)pl->Z * pl->res * rbytes(pl->p.plane_dtype);
+  const int64_t per_bin = plane_buffer_bytes(pl, 1);  // 9/8 of a value per column: a whole number of bytes per bin
   std::vector<std::pair<int32_t, int32_t>> chunks;
   for (int32_t i = 0; i < n;) {
     int64_t samples = 0, bytes = 0;
@@ -737,7 +772,7 @@ fdas_status fdas_autotune(const fdas_params* base, int device, void* hip_stream,
     }
     const int64_t nb = p.n_samples / 2;
     const int64_t spec_bytes = align256(nb * cbytes(p.store_dtype));
-    const int64_t plane_bytes = align256(nb * pl->Z * pl->res * rbytes(p.plane_dtype));
+    const int64_t plane_bytes = align256(plane_buffer_bytes(pl, nb));
     const int64_t need = pl->total + spec_bytes + plane_bytes;
     if (need > scratch_bytes) {
       g_plan_error = "autotune scratch too small: need " + std::to_string(need) + " bytes";

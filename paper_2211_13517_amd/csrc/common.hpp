@@ -83,6 +83,26 @@ template <> struct Store<FDAS_F16> {
   __device__ __forceinline__ static float unpack_real(real_t v) { return (float)__builtin_bit_cast(_Float16, v); }
 };
 
+// Column maxima of a plane are taken on bit patterns: for a non-negative
+// value (+inf included) the pattern read as an unsigned integer orders like
+// the value, and every other pattern (a NaN, or a sign bit) is capped at
+// +inf's, so that it counts as +inf; a maximum is then an upper bound of
+// every value of its run, whatever the values are.
+template <int PDT>
+__device__ __forceinline__ uint32_t capped_bits(typename Store<PDT>::real_t x) {
+  if constexpr (PDT == FDAS_F32)
+    return min(__float_as_uint(x), 0x7f800000u);
+  else
+    return min((uint32_t)x, PDT == FDAS_BF16 ? 0x7f80u : 0x7c00u);
+}
+template <int PDT>
+__device__ __forceinline__ typename Store<PDT>::real_t from_bits(uint32_t b) {
+  if constexpr (PDT == FDAS_F32)
+    return __uint_as_float(b);
+  else
+    return (typename Store<PDT>::real_t)b;
+}
+
 // Orders LDS traffic of one wavefront: LDS operations of a wavefront complete
 // in issue order, so a compiler-level barrier is all a wave-private exchange
 // buffer needs between its writes and the reads of other lanes.

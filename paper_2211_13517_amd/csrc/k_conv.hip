@@ -2,16 +2,19 @@
 // fused in one kernel so that the complex products never leave the chip.
 //
 // Work unit ("tile"): one segment of one series and one group of templates.
-// Segment s of a series covers spectrum bins [s U - h_max, s U - h_max + L)
-// (zero outside [0, N/2)).  The tile loads it once, runs the forward FFT and
-// keeps the result F in registers; then, for each template j of its group,
-// multiplies F by the template spectrum T_j (read from L2, it is shared by
-// every tile), runs the inverse FFT and stores |y|^2 of the U = L - 2 h_max
-// outputs free of wrap-around, at plane[j][s U + i].
+// Segment s of a series covers spectrum bins [s U - h', s U - h' + L) (zero
+// outside [0, N/2)), h' = h_max rounded up to a multiple of 8.  The tile
+// loads it once, runs the forward FFT and keeps the result F in registers;
+// then, for each template j of its group, multiplies F by the template
+// spectrum T_j (read from L2, it is shared by every tile), runs the inverse
+// FFT and stores |y|^2 of U outputs free of wrap-around (U the largest
+// multiple of 8 <= L - 2 h'), at plane[j][s U + i], and the maximum of each
+// aligned run of 8 of them in the column-maxima section of the plane buffer.
 //
-// Half-bin plane: U = L - 2 h_max - 1, so output i + 1 is free of wrap-around
-// too, and each output stores the pair (|y_i|^2, |y_i - y_{i+1}|^2 / 2) at
-// columns 2(s U + i) and 2(s U + i) + 1 of a row twice as long.  Output i sits
+// Half-bin plane: h' and U are multiples of 4 and U <= L - 2 h' - 1, so
+// output i + 1 is free of wrap-around too, and each output stores the pair
+// (|y_i|^2, |y_i - y_{i+1}|^2 / 2) at columns 2(s U + i) and 2(s U + i) + 1
+// of a row twice as long; a column maximum covers 4 outputs.  Output i sits
 // in thread i mod NT, register i / NT; its successor is the next lane's
 // register (a cross-lane shuffle), for the last lane of a wavefront the first
 // lane of the next wavefront (through LDS in block tiles), and for the last
@@ -76,6 +79,26 @@ __device__ __forceinline__ void next_outputs(const c32 (&v)[FS::P], c32 (&nx)[FS
   }
 }
 
+// Column maxima (on capped bit patterns, see capped_bits) of aligned groups
+// of G lanes (4 or 8), over every register at once so that the DPP steps of
+// different registers interleave: lane swaps within quads give every lane of
+// a quad its quad's maximum; for G = 8 a shift by 4 lanes within each row of
+// 16 then gives lanes 4..7 of each group the group's maximum (lanes 0..3 of
+// a row read 0 and keep theirs).  The group's lane G/2 holds it.
+template <int G, int P>
+__device__ __forceinline__ void group_max(uint32_t (&v)[P]) {
+  auto step = [&](auto ctrl) {
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      // a lane with no source lane reads 0, which leaves its maximum as it is
+      v[c] = max(v[c], (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[c], decltype(ctrl)::value, 0xF, 0xF, true));
+    });
+  };
+  step(std::integral_constant<int, 0xB1>{});  // quad_perm [1, 0, 3, 2]
+  step(std::integral_constant<int, 0x4E>{});  // quad_perm [2, 3, 0, 1]
+  if constexpr (G == 8) step(std::integral_constant<int, 0x114>{});  // row_shr:4
+}
+
 // A bin's power and the half-bin power after it, as one store.
 template <int PDT> struct PowerPair;
 template <> struct PowerPair<FDAS_F32> {
@@ -104,7 +127,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
   const int64_t local = tile - d.tile_begin;
   const int seg = (int)(local / a.G), grp = (int)(local % a.G);
   const int t0 = (int)(((int64_t)grp * a.Z) / a.G), t1 = (int)(((int64_t)(grp + 1) * a.Z) / a.G);
-  const int r0 = seg * a.U - a.hmax;  // bin of FFT index 0 (segment start, may be negative)
+  const int r0 = seg * a.U - a.seg_margin;  // bin of FFT index 0 (segment start, may be negative)
   const CT* sp = reinterpret_cast<const CT*>(a.spec) + d.spec_off;
 
   // Segment load: indices outside [0, nbins) read a clamped address and are zeroed.
@@ -121,8 +144,15 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
 
   const CT* T = reinterpret_cast<const CT*>(a.tspec);
   RT* out = reinterpret_cast<RT*>(a.plane) + d.plane_off;
-  // Output index i maps to bin r0 + i; valid for i in [lo, hi).
-  const int lo = a.hmax, hi = min(a.hmax + a.U, d.nbins - r0);
+  RT* mx = reinterpret_cast<RT*>(a.maxima) + d.plane_off / kPlaneMaxCols;
+  // Output index i maps to bin r0 + i; valid for i in [lo, hi).  r0, lo and
+  // hi are multiples of the bins per column maximum (G8 = 8, or 4 on a
+  // half-bin plane), so the G8 outputs of an aligned group of lanes are all
+  // valid or all not, and make one maximum.
+  const int lo = a.seg_margin, hi = min(a.seg_margin + a.U, d.nbins - r0);
+  constexpr int G8 = IB ? kPlaneMaxCols / 2 : kPlaneMaxCols;
+  const int grp0 = tid & ~(G8 - 1);           // first lane of this lane's group
+  const bool lead = (tid & (G8 - 1)) == G8 / 2;  // the lane that stores the group's maximum
   const uint32_t toff = (uint32_t)tid * sizeof(CT);
   CT tc[P];
   static_for<0, P>([&](auto cc) {
@@ -149,23 +179,50 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
       using PP = PowerPair<PDT>;
       typename PP::type* dst =
           reinterpret_cast<typename PP::type*>(out + (size_t)t * (2u * (uint32_t)d.nbins)) + (r0 + tid);
+      // maxima of row t: 2 nbins / 8 per row; group g of register c (the
+      // lanes from grp0) at column (r0 + grp0 + NT c) / 4
+      RT* mdst = mx + (size_t)t * (uint32_t)(d.nbins / G8) + (r0 + grp0) / G8;
+      float p[P], h[P];
+      uint32_t m[P];
+      static_for<0, P>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const c32 dv = {v[c].re - nx[c].re, v[c].im - nx[c].im};
+        p[c] = cnorm(v[c]);
+        h[c] = 0.5f * cnorm(dv);
+        m[c] = max(capped_bits<PDT>(PS::pack_real(p[c])), capped_bits<PDT>(PS::pack_real(h[c])));
+      });
+      group_max<G8>(m);
       static_for<0, P>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         if (NT * c + NT - 1 < lo || NT * c >= hi) return;
         const int i = tid + NT * c;
-        const c32 dv = {v[c].re - nx[c].re, v[c].im - nx[c].im};
-        if (i >= lo && i < hi) dst[NT * c] = PP::pack(cnorm(v[c]), 0.5f * cnorm(dv));
+        if (i >= lo && i < hi) {
+          dst[NT * c] = PP::pack(p[c], h[c]);
+          if (lead) mdst[NT / G8 * c] = from_bits<PDT>(m[c]);
+        }
       });
     } else {
       // this thread's output i = tid + NT c lands at bin r0 + i of row t: one
       // 64-bit pointer per template, the register index as an immediate offset
       RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + tid);
+      RT* mdst = mx + (size_t)t * (uint32_t)(d.nbins / G8) + (r0 + grp0) / G8;
+      RT p[P];
+      uint32_t m[P];
+      static_for<0, P>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        p[c] = PS::pack_real(cnorm(v[c]));
+        m[c] = capped_bits<PDT>(p[c]);
+      });
+      group_max<G8>(m);
       static_for<0, P>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         // the register is out of range for every thread: skip (uniform branch)
         if (NT * c + NT - 1 < lo || NT * c >= hi) return;
         const int i = tid + NT * c;
-        if (i >= lo && i < hi) dst[NT * c] = PS::pack_real(cnorm(v[c]));
+        if (i >= lo && i < hi) {
+          dst[NT * c] = p[c];
+          if (lead) mdst[NT / G8 * c] = from_bits<PDT>(m[c]);
+        }
       });
     }
     static_for<0, P>([&](auto cc) { tc[decltype(cc)::value] = tn[decltype(cc)::value]; });

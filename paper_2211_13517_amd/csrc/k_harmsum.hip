@@ -53,25 +53,44 @@ __device__ inline double sigma_from_log_tail(double lq) {
 //   base_k + rel_k(t),  base_k = j0 + 16 k u / H,
 // with rel_k(t) = floor((2kt + H)/(2H)) for u >= 0 and ceil((2kt - H)/(2H))
 // for u < 0: a compile-time pattern.  Likewise harmonic k of cell R0 + i
-// reads bin k R0 / H + floor((2ki + H)/(2H)).  The block copies, for every
-// k below the top two, the rows base_k .. base_k + rows(k) - 1 of the bin
-// strip it needs into LDS with aligned 16-byte loads, synchronises once, and
-// then evaluates its CW x 16 cells with LDS reads whose offsets are all
-// immediates.  The top two harmonics use (nearly) one value per cell, so
-// each thread loads those straight into registers; that keeps a tile's LDS
-// at 34 KB (four blocks per CU instead of three).
+// reads bin k R0 / H + floor((2ki + H)/(2H)).
+//
+// Bound first, exact sums where the bound passes.  The plane buffer carries
+// the column maxima M[j][c] = max_{q < 8} P[j][8c + q] after its data.  The
+// block copies into LDS, for the lower half of the harmonics (k <= H/2), the
+// strip of plane values it reads, and for the upper half (k > H/2, whose
+// strips are the largest: together they hold 5/6 of the tile's reads at
+// H = 16) the strip of column maxima covering theirs, 8 times smaller.  With
+// each upper-half value replaced by the maximum of its run of 8 columns, the
+// stage sums S'_H' are upper bounds of the exact S_H': the terms only grow
+// and every operation of the sum (FP32 additions, and products by 1 in the
+// two-term dot products of 16-bit planes) is monotone in each operand.  So
+// a cell whose bounds all stay below their thresholds passes no stage, and
+// only the few cells with a bound at or above one (about 3e-5 of them on
+// pure noise at H = 16) load their upper-half values from the plane and sum
+// exactly, in the same order as everywhere, and are tested and reported
+// from those exact sums.  Every strip is copied with aligned 16-byte loads
+// and read back with LDS offsets that are immediates.
 constexpr int kBand = 16;
+constexpr int kMaxCols = kPlaneMaxCols;
 
-template <int H, int CW, int CH, int ND>
+template <int H, int CW, int CH>
 struct HarmTile {
-  static constexpr int KL = H - ND;  // harmonics staged in LDS (the top ND are read directly)
+  static constexpr int KX = H / 2;  // k <= KX: plane values; k > KX: column maxima
   static constexpr int rows(int k) { return (2 * k * (kBand - 1) + H) / (2 * H) + 1; }
-  // bins of harmonic k read by the tile: 0 .. floor((2k(CW-1) + H)/(2H))
+  // bins of harmonic k read by the tile: 0 .. floor((2k(CW-1) + H)/(2H)),
+  // from bin k R0 / H, a multiple of kMaxCols and of CH
   static constexpr int span(int k) { return (2 * k * (CW - 1) + H) / (2 * H) + 1; }
-  static constexpr int chunks(int k) { return (span(k) + CH - 1) / CH; }          // 16-byte chunks per strip row
-  static constexpr int pitch(int k) { return chunks(k) * CH; }                     // elements per strip row
+  // column maxima covering the span
+  static constexpr int mspan(int k) { return (span(k) - 1) / kMaxCols + 1; }
+  // 16-byte chunks per strip row; a maxima strip starts at the aligned
+  // element at or below its first maximum, up to CH - 1 elements early
+  static constexpr int chunks(int k) {
+    return k <= KX ? (span(k) + CH - 1) / CH : (mspan(k) + 2 * CH - 2) / CH;
+  }
+  static constexpr int pitch(int k) { return chunks(k) * CH; }  // elements per strip row
   static constexpr int off(int k) { return k <= 1 ? 0 : off(k - 1) + rows(k - 1) * pitch(k - 1); }
-  static constexpr int SIZE = off(KL + 1);                                          // elements of LDS
+  static constexpr int SIZE = off(H + 1);  // elements of LDS
   // strip row of harmonic k for trial t of a band below (neg) or above z = 0
   static constexpr int rel(int k, int t, bool neg) {
     return neg ? (2 * k * t - H <= 0 ? 0 : (2 * k * t - H + 2 * H - 1) / (2 * H)) : (2 * k * t + H) / (2 * H);
@@ -80,7 +99,7 @@ struct HarmTile {
 
 template <int PDT>
 struct HarmCfg {
-  static constexpr int CW = Store<PDT>::RBYTES == 2 ? 256 : 128;  // cells per tile = threads per block
+  static constexpr int CW = 256;  // cells per tile = threads per block
   // Tile order: groups of GROUP bands (48 trials) are swept over all column
   // tiles, the bands of a group interleaved.  Bands that are close in z
   // share the rows of the low harmonics, and a sweep's working set then
@@ -228,16 +247,16 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   using PS = Store<PDT>;
   using RT = typename PS::real_t;
   constexpr int NST = ilog2(H) + 1;
-  constexpr int CH = 16 / (int)sizeof(RT);
+  constexpr int ES = (int)sizeof(RT);
+  constexpr int CH = 16 / ES;
   constexpr int CW = HarmCfg<PDT>::CW, G = HarmCfg<PDT>::GROUP;
-  // The top ND harmonics read (nearly) one value per cell: they bypass LDS
-  // and are loaded by each thread straight into registers.
-  constexpr int ND = H >= 4 ? 2 : 0;
-  using HT = HarmTile<H, CW, CH, ND>;
+  using HT = HarmTile<H, CW, CH>;
+  static_assert(HT::SIZE * ES <= 32768, "strips of one tile");
   __shared__ __align__(16) RT strip[HT::SIZE];
 
   const SeriesDesc d = a.desc[blockIdx.z];
   const int nb = d.nbins << a.res_shift;  // plane columns of the series
+  const int nm = nb / kMaxCols;           // column maxima per row
   const int ncol = (a.max_bins + CW - 1) / CW;  // column tiles of the longest series
   const int tile = xcd_tile(blockIdx.x);
   const int grp = tile / (ncol * G), inner = tile % (ncol * G);
@@ -248,75 +267,57 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   const int t_lo = max(0, -jt0), t_hi = min(kBand, a.Z - jt0);
   const int tid = threadIdx.x;
   const RT* plane = reinterpret_cast<const RT*>(a.plane) + d.plane_off;
+  const RT* maxima = reinterpret_cast<const RT*>(a.maxima) + d.plane_off / kMaxCols;
 
   // Copy the strips with direct global-to-LDS 16-byte loads: item f of
-  // harmonic k (row f / NCH, chunk f % NCH) lands at byte off(k) * sizeof(RT)
-  // + 16 f, so a wave's 64 items are contiguous in LDS from a wave-uniform
-  // base, and every load of the block is in flight before the one wait at
-  // the barrier.  Rows outside the plane are never read by a valid trial.
+  // harmonic k (row f / NCH, chunk f % NCH) lands at byte off(k) * ES + 16 f,
+  // so a wave's 64 items are contiguous in LDS from a wave-uniform base, and
+  // every load of the block is in flight before the one wait at the barrier.
+  // Rows outside the plane are never read by a valid trial, nor chunks past
+  // the row's end by a searched cell.
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
-  static_for<1, HT::KL + 1>([&](auto kc) {
+  static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
     const int base = a.j0 + (kBand / H) * k * u;
     const int cs = k * (R0 / H);
-    // wave-uniform 64-bit base (row base_k, bin cs) plus a 32-bit byte offset
-    // per lane, the form the load's scalar-base addressing takes
-    const char* src = reinterpret_cast<const char*>(plane + ((int64_t)base * nb + cs));
+    const bool ex = k <= HT::KX;
+    const int c0 = ex ? cs : (cs / kMaxCols) & ~(CH - 1);  // first element of the strip's rows
+    const int len = ex ? nb : nm;                           // elements per source row
+    // wave-uniform 64-bit base (row base_k, element c0) plus a 32-bit byte
+    // offset per lane, the form the load's scalar-base addressing takes
+    const char* src = reinterpret_cast<const char*>((ex ? plane : maxima) + ((int64_t)base * len + c0));
 #pragma unroll
     for (int f0 = 0; f0 < ITEMS; f0 += CW) {
       if (f0 + wave0 >= ITEMS) continue;  // wave-uniform
       const int f = f0 + tid;
       const int r = f / NCH, c = f - r * NCH;
-      const int row = base + r, e0 = cs + c * CH;
-      if (f < ITEMS && row >= 0 && row < a.Z && e0 < nb)
-        load_lds16(src + (uint32_t)((r * nb + c * CH) * (int)sizeof(RT)),
-                   reinterpret_cast<char*>(strip) + HT::off(k) * (int)sizeof(RT) + (f0 + wave0) * 16);
+      const int row = base + r, e0 = c0 + c * CH;
+      if (f < ITEMS && row >= 0 && row < a.Z && e0 < len)
+        load_lds16(src + (uint32_t)((r * len + c * CH) * ES),
+                   reinterpret_cast<char*>(strip) + HT::off(k) * ES + (f0 + wave0) * 16);
     }
   });
-  // The directly read harmonics: this thread's bin of each of their rows
-  // (rows outside the plane and bins past the series are clamped: their
-  // values only reach cells that are not searched).
-  auto raw = [](const RT* p) -> uint32_t {
-    if constexpr (sizeof(RT) == 4)
-      return *reinterpret_cast<const uint32_t*>(p);
-    else
-      return *reinterpret_cast<const uint16_t*>(p);
-  };
-  auto direct_ptr = [&](int k, int rel) {
-    const int cs = k * (R0 / H);
-    const int row = min(max(a.j0 + (kBand / H) * k * u + rel, 0), a.Z - 1);  // uniform
-    const int pos = min((2 * k * tid + H) / (2 * H), nb - 1 - cs);
-    return reinterpret_cast<const RT*>(reinterpret_cast<const char*>(plane + ((int64_t)row * nb + cs)) +
-                                       (uint32_t)(pos * (int)sizeof(RT)));
-  };
-  uint32_t dv[ND > 0 ? ND : 1][kBand];
-  auto dload = [&](auto negc) {
-    constexpr bool NEG = decltype(negc)::value;
-    static_for<0, ND>([&](auto dc) {
-      constexpr int k = H - decltype(dc)::value;
-      static_for<0, kBand>([&](auto tc) {
-        constexpr int t = decltype(tc)::value;
-        dv[decltype(dc)::value][t] = raw(direct_ptr(k, HT::rel(k, t, NEG)));
-      });
-    });
-  };
-  if (u < 0)
-    dload(std::true_type{});
-  else
-    dload(std::false_type{});
   __syncthreads();
 
   const int R = R0 + tid;
   if (R >= nb - a.hmax) return;
-  // byte offset of this cell's harmonic-k bin in row 0 of strip k; kept
-  // opaque so that the compiler holds it in a register and folds every row
-  // offset into the LDS instruction's immediate
+  // byte offset of this cell's harmonic-k value (plane value or column
+  // maximum) in row 0 of strip k; kept opaque so that the compiler holds it
+  // in a register and folds every row offset into the LDS instruction's
+  // immediate
   const char* lds = reinterpret_cast<const char*>(strip);
   int boff[H];
-  static_for<1, HT::KL + 1>([&](auto kc) {
+  static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    int b = (HT::off(k) + (2 * k * tid + H) / (2 * H)) * (int)sizeof(RT);
+    const int e = (2 * k * tid + H) / (2 * H);
+    int b;
+    if constexpr (k <= HT::KX) {
+      b = (HT::off(k) + e) * ES;
+    } else {
+      const int ms = k * (R0 / H) / kMaxCols;
+      b = (HT::off(k) + (ms & (CH - 1)) + e / kMaxCols) * ES;
+    }
     asm volatile("" : "+v"(b));
     boff[k - 1] = b;
   });
@@ -330,29 +331,25 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     thr[st] = en[st] ? a.tau[st] : __builtin_inff();
   }
   const uint32_t thr0_bits = ceil_bits16<PDT>(thr[0]);
-  // wave-wide pass masks per trial (scalar registers)
+  // wave-wide masks per trial (scalar registers) of the cells whose bound
+  // passes a stage
   unsigned long long bal[kBand];
+  auto none = [](auto) { return 0u; };
   auto band = [&](auto negc) {
     constexpr bool NEG = decltype(negc)::value;
     auto offs = [](auto tc) {
       return [](auto kc) {
         constexpr int k = decltype(kc)::value, t = decltype(tc)::value;
-        return HT::rel(k, t, NEG) * HT::pitch(k) * (int)sizeof(RT);
+        return HT::rel(k, t, NEG) * HT::pitch(k) * ES;
       };
     };
     // software pipeline: the LDS reads of trial t + 1 are issued before the
     // sums of trial t (every trial's reads stay inside the strips)
-    auto dir = [&](auto tc) {
-      return [&](auto kc) { return dv[H - decltype(kc)::value][decltype(tc)::value]; };
-    };
-    HarmVals<H> cur = load_vals<PDT, H, HT::KL>(lds, boff, offs(std::integral_constant<int, 0>{}),
-                                               dir(std::integral_constant<int, 0>{}));
+    HarmVals<H> cur = load_vals<PDT, H, H>(lds, boff, offs(std::integral_constant<int, 0>{}), none);
     static_for<0, kBand>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       HarmVals<H> nxt;
-      if constexpr (t + 1 < kBand)
-        nxt = load_vals<PDT, H, HT::KL>(lds, boff, offs(std::integral_constant<int, t + 1>{}),
-                                        dir(std::integral_constant<int, t + 1>{}));
+      if constexpr (t + 1 < kBand) nxt = load_vals<PDT, H, H>(lds, boff, offs(std::integral_constant<int, t + 1>{}), none);
       bal[t] = 0;
       if (t >= t_lo && t < t_hi) bal[t] = pass_mask<PDT, H>(cur, thr, thr0_bits);
       if constexpr (t + 1 < kBand) cur = nxt;
@@ -363,7 +360,8 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   else
     band(std::false_type{});
 
-  // rare: cells with a passing stage report their most significant one
+  // rare: cells whose bound passes sum exactly (upper-half values from the
+  // plane) and report their most significant passing stage
   unsigned long long any = 0;
 #pragma unroll
   for (int t = 0; t < kBand; ++t) any |= bal[t];
@@ -373,20 +371,29 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
 #pragma unroll
   for (int t = 0; t < kBand; ++t) mask |= (uint32_t)((bal[t] >> lane) & 1ull) << t;
   const bool neg = u < 0;
+  auto raw = [](const RT* p) -> uint32_t {
+    if constexpr (ES == 4)
+      return *reinterpret_cast<const uint32_t*>(p);
+    else
+      return *reinterpret_cast<const uint16_t*>(p);
+  };
   while (mask) {
     const int t = __builtin_ctz(mask);
     mask &= mask - 1;
     const int j = jt0 + t;
     float S[NST];
-    const HarmVals<H> x = load_vals<PDT, H, HT::KL>(
+    const HarmVals<H> x = load_vals<PDT, H, HT::KX>(
         lds, boff,
         [&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          return HT::rel(k, t, neg) * HT::pitch(k) * (int)sizeof(RT);
+          return HT::rel(k, t, neg) * HT::pitch(k) * ES;
         },
         [&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          return raw(direct_ptr(k, HT::rel(k, t, neg)));
+          // a valid trial's row and a searched cell's bin are inside the plane
+          const int row = a.j0 + (kBand / H) * k * u + HT::rel(k, t, neg);
+          const int bin = k * (R0 / H) + (2 * k * tid + H) / (2 * H);
+          return raw(plane + ((int64_t)row * nb + bin));
         });
     stage_sums<PDT, H>(x, [&](int st, float v) { S[st] = v; });
     double best = 0.0;
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
         bi = st;
       }
     }
-    if (bi < 0) continue;  // only an infinite sum at an unsearched stage gets here
+    if (bi < 0) continue;  // the bound passed, the exact sums do not
     const unsigned long long slot = atomicAdd(a.count, 1ull);
     if ((int64_t)slot < a.capacity) {
       const int hh = 1 << bi;
@@ -448,6 +455,46 @@ static hipError_t hs_h(const HarmArgs& a, dim3 g, hipStream_t st) {
     case 4: hs_launch<PDT, 4>(a, g, st); break;
     case 8: hs_launch<PDT, 8>(a, g, st); break;
     case 16: hs_launch<PDT, 16>(a, g, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Column maxima of a packed plane: M[j][c] is the largest of P[j][8c + q],
+// q < 8, a NaN or negative value counting as +inf (see capped_bits).
+// Maximum i of a series is row i / nm, column i % nm, and its run is the 8
+// consecutive plane elements from 8 i.
+template <int PDT>
+__global__ __launch_bounds__(256) void k_plane_maxima(const void* __restrict__ plane, void* __restrict__ maxima,
+                                                      const SeriesDesc* __restrict__ desc, int Z, int res_shift) {
+  using RT = typename Store<PDT>::real_t;
+  constexpr int V = 16 / (int)sizeof(RT);  // elements per 16-byte load
+  const SeriesDesc d = desc[blockIdx.y];
+  const int64_t n = (int64_t)Z * ((int64_t)(d.nbins << res_shift) / kMaxCols);
+  const RT* p = reinterpret_cast<const RT*>(plane) + d.plane_off;
+  RT* m = reinterpret_cast<RT*>(maxima) + d.plane_off / kMaxCols;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int h = 0; h < kMaxCols / V; ++h) {
+      const uint4 w = *reinterpret_cast<const uint4*>(p + kMaxCols * i + V * h);
+      const RT* e = reinterpret_cast<const RT*>(&w);
+#pragma unroll
+      for (int q = 0; q < V; ++q) v = max(v, capped_bits<PDT>(e[q]));
+    }
+    m[i] = from_bits<PDT>(v);
+  }
+}
+
+hipError_t launch_plane_maxima(int pdt, const void* plane, void* maxima, const SeriesDesc* desc, int n_series, int Z,
+                               int res_shift, int64_t max_bins, int cus, hipStream_t st) {
+  const int64_t per_series = (int64_t)Z * ((max_bins << res_shift) / kMaxCols);
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((per_series + 255) / 256, (int64_t)cus * 16)),
+               (unsigned)n_series);
+  switch (pdt) {
+    case FDAS_F32: hipLaunchKernelGGL(k_plane_maxima<FDAS_F32>, g, dim3(256), 0, st, plane, maxima, desc, Z, res_shift); break;
+    case FDAS_BF16: hipLaunchKernelGGL(k_plane_maxima<FDAS_BF16>, g, dim3(256), 0, st, plane, maxima, desc, Z, res_shift); break;
+    case FDAS_F16: hipLaunchKernelGGL(k_plane_maxima<FDAS_F16>, g, dim3(256), 0, st, plane, maxima, desc, Z, res_shift); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -56,15 +56,23 @@ hipError_t launch_template_taps(double z_min, double z_step, int Z, int margin, 
 hipError_t launch_template_spectra(int sdt, const c64* taps, const c64* tab, int Z, int hmax, int L, void* out,
                                    hipStream_t st);
 
+// Column maxima: a plane buffer holds the batch's plane values, then for
+// every row of every series the maximum of each run of kPlaneMaxCols columns
+// (series i's maxima from element plane_off / kPlaneMaxCols of that section).
+constexpr int kPlaneMaxCols = 8;
+
 // convolution
 struct ConvArgs {
   const void* spec;        // packed normalised spectrum, store dtype
   const void* tspec;       // template spectra [Z][L], store dtype
   void* plane;             // packed planes, plane dtype
+  void* maxima;            // their column maxima, plane dtype
   const SeriesDesc* desc;  // per series
   const c32* tw;           // twiddle table of size L
   int64_t n_tiles;         // sum over series of nseg * G
-  int32_t n_series, Z, G, U, hmax;
+  // seg_margin: FFT index of a segment's first output (>= h_max; it and U
+  // are multiples of the bins per column maximum)
+  int32_t n_series, Z, G, U, seg_margin;
 };
 // interbin: also write the half-bin power between each output and the next
 // R: radix of the convolution FFT's passes (16; 8 or 4 at L = 1024)
@@ -75,9 +83,13 @@ bool conv_radix_supported(int L, int R);
 int conv_twiddle_size(int L, int R);           // entries of the convolution FFT's twiddle table
 void conv_twiddle_fill(int L, int R, c32* dst);
 
+hipError_t launch_plane_maxima(int pdt, const void* plane, void* maxima, const SeriesDesc* desc, int n_series, int Z,
+                               int res_shift, int64_t max_bins, int cus, hipStream_t st);
+
 // harmonic sums
 struct HarmArgs {
   const void* plane;
+  const void* maxima;  // column maxima of the plane
   const SeriesDesc* desc;
   fdas_candidate* cands;
   unsigned long long* count;

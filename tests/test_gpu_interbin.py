@@ -211,8 +211,8 @@ def test_interbin_ska_full_size_sampled(lib):
 
 def test_interbin_argument_errors_enqueue_nothing(lib):
     """Host-side checks of the half-bin path: a plane buffer sized for the bin
-    plane, or misaligned for (bin, half-bin) pairs, is refused before any
-    launch and leaves the buffer untouched."""
+    plane, or not 16-byte aligned, is refused before any launch and leaves
+    the buffer untouched."""
     import ctypes
     import torch
     n = 1 << 17
@@ -223,10 +223,11 @@ def test_interbin_argument_errors_enqueue_nothing(lib):
     small = torch.full((pl.Z * n // 2,), -1.0, device="cuda")            # bin-plane size: too small
     with pytest.raises(lib.FdasError, match="too small"):
         pl.convolve_spectrum(spec, [n], plane=small)
-    big = torch.full((pl.Z * n + 1,), -1.0, device="cuda")
+    need = pl.Z * n * 9 // 8                                              # values and column maxima
+    big = torch.full((need + 4,), -1.0, device="cuda")
     lens = (ctypes.c_int64 * 1)(n)
     st = pl.lib.fdas_convolve_spectrum(pl.handle, ctypes.c_void_p(spec.data_ptr()), lens, 1,
-                                       ctypes.c_void_p(big.data_ptr() + 4), (pl.Z * n) * 4)
+                                       ctypes.c_void_p(big.data_ptr() + 8), need * 4)
     assert st == 1 and b"aligned" in pl.lib.fdas_last_error(pl.handle)
     torch.cuda.synchronize()
     assert bool((small == -1.0).all()) and bool((big == -1.0).all())
