@@ -122,6 +122,15 @@ __device__ __forceinline__ int xcd_tile(int b) {
 
 __device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0 ? a : a - b + 1) / b; }
 
+// f / D for 0 <= f < 2^11 and D <= 64, exactly, by a full-rate 24-bit
+// multiply: with M = ceil(2^20 / D), f M / 2^20 exceeds f / D by less than
+// f (D - 1) / (2^20 D) < 1 / D, which cannot reach the next integer.
+template <int D>
+__device__ __forceinline__ int div_small(int f) {
+  constexpr unsigned M = ((1u << 20) + D - 1) / D;
+  return (int)(__umul24((unsigned)f, M) >> 20);
+}
+
 // Nested stage sums: stage 0 is harmonic H alone; stage st adds the odd
 // multiples of H / 2^st, so the sum handed to sink(st, S) covers
 // k = H/2^st, 2 H/2^st, ..., H.
@@ -275,10 +284,15 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
   // every load of the block is in flight before the one wait at the barrier.
   // Rows outside the plane are never read by a valid trial, nor chunks past
   // the row's end by a searched cell.
+  // The item arithmetic uses full-rate 24-bit multiplies; on an interior
+  // tile (every trial valid, the strips' last chunks well inside the rows)
+  // every item is loaded without bounds tests.
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+  const bool interior = t_lo == 0 && t_hi == kBand && R0 + 2 * CW <= nb;
   static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
+    static_assert(ITEMS < 2048 && NCH <= 64, "item index arithmetic");
     const int base = a.j0 + (kBand / H) * k * u;
     const int cs = k * (R0 / H);
     const bool ex = k <= HT::KX;
@@ -291,11 +305,13 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
     for (int f0 = 0; f0 < ITEMS; f0 += CW) {
       if (f0 + wave0 >= ITEMS) continue;  // wave-uniform
       const int f = f0 + tid;
-      const int r = f / NCH, c = f - r * NCH;
-      const int row = base + r, e0 = c0 + c * CH;
-      if (f < ITEMS && row >= 0 && row < a.Z && e0 < len)
-        load_lds16(src + (uint32_t)((r * len + c * CH) * ES),
-                   reinterpret_cast<char*>(strip) + HT::off(k) * ES + (f0 + wave0) * 16);
+      const int r = div_small<NCH>(f), c = f - (int)__umul24(r, NCH);
+      const bool inside = (unsigned)(base + r) < (unsigned)a.Z && c0 + c * CH < len;
+      if (f < ITEMS && (interior || inside)) {
+        uint32_t e = __umul24(r, len) + c * CH;  // element offset (< 2^27)
+        asm volatile("" : "+v"(e));              // (keeps the 24-bit multiply)
+        load_lds16(src + e * ES, reinterpret_cast<char*>(strip) + HT::off(k) * ES + (f0 + wave0) * 16);
+      }
     }
   });
   __syncthreads();
