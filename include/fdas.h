@@ -230,7 +230,12 @@ fdas_status fdas_plane_maxima(fdas_plan_t plan, void *plane, const int64_t *leng
  * bounded with each term k > H/2 replaced by the column maximum over its
  * run of 8 columns; only cells with a bound at or above a threshold read
  * those terms from the plane and sum exactly, in the same order, so the
- * records are those of the exact sums (stale maxima would lose detections). */
+ * records are those of the exact sums (stale maxima would lose detections).
+ * The maxima are read where this call's batch puts them, so the plan must
+ * have written them for this plane buffer and batch (its convolution entry
+ * points, fdas_search or fdas_plane_maxima, among its last 8 such writes):
+ * otherwise FDAS_ERR_STATE and nothing is enqueued.  Plane values changed
+ * after that need fdas_plane_maxima again. */
 fdas_status fdas_harmonic_sum(fdas_plan_t plan, const void *plane, const int64_t *lengths_host,
                               int32_t n_series, fdas_candidate *cands, int64_t capacity,
                               int64_t *d_count);

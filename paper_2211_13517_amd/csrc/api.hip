@@ -95,6 +95,16 @@ struct fdas_plan_s {
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uintptr_t> graph_key;
   hipError_t static_table_status = hipSuccess;  // look-up of the static clustering table at plan time
+  // plane buffers whose column maxima this plan wrote (convolution or
+  // fdas_plane_maxima), with the batch they were written for: the harmonic
+  // sum reads the maxima where its own batch puts them, so it refuses a
+  // buffer and batch that no maxima were written for
+  struct MaximaWrite {
+    uintptr_t plane = 0;
+    uint64_t batch = 0;
+  };
+  MaximaWrite maxima_writes[8];
+  int maxima_next = 0;
 
   fdas_status fail(fdas_status s, const std::string& m) {
     err = m;
@@ -468,6 +478,30 @@ static int64_t plane_buffer_bytes(fdas_plan_t pl, int64_t bins) {
   return plane_data_bytes(pl, bins) + plane_data_bytes(pl, bins) / kPlaneMaxCols;
 }
 static int64_t plane_need(fdas_plan_t pl) { return plane_buffer_bytes(pl, pl->total_bins); }
+
+// FNV-1a over the current batch's lengths (the plane layout they give).
+static uint64_t batch_key(fdas_plan_t pl) {
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t v : pl->key_lengths)
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  return h ^ (uint64_t)pl->key_lengths.size();
+}
+static void note_maxima_written(fdas_plan_t pl, const void* plane) {
+  const uint64_t k = batch_key(pl);
+  for (auto& w : pl->maxima_writes)
+    if (w.plane == (uintptr_t)plane && w.batch == k) return;
+  pl->maxima_writes[pl->maxima_next] = {(uintptr_t)plane, k};
+  pl->maxima_next = (pl->maxima_next + 1) % 8;
+}
+static bool maxima_written(fdas_plan_t pl, const void* plane) {
+  const uint64_t k = batch_key(pl);
+  for (const auto& w : pl->maxima_writes)
+    if (w.plane == (uintptr_t)plane && w.batch == k) return true;
+  return false;
+}
 static void* plane_maxima(fdas_plan_t pl, const void* plane) {
   return const_cast<char*>(reinterpret_cast<const char*>(plane)) + plane_data_bytes(pl, pl->total_bins);
 }
@@ -527,6 +561,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   hipError_t e =
       launch_conv(pl->L, pl->p.fft_radix, pl->p.store_dtype, pl->p.plane_dtype, pl->p.interbin != 0, a, grid, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "convolve");
+  note_maxima_written(pl, plane);
   return FDAS_OK;
 }
 
@@ -586,6 +621,7 @@ fdas_status fdas_plane_maxima(fdas_plan_t pl, void* plane, const int64_t* length
                           reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc), (int)pl->desc.size(), pl->Z,
                           pl->res == 2 ? 1 : 0, pl->max_bins, pl->cu_count, pl->stream);
   if (e != hipSuccess) return hip_fail(pl, e, "column maxima");
+  note_maxima_written(pl, plane);
   return FDAS_OK;
 }
 
@@ -601,6 +637,10 @@ fdas_status fdas_harmonic_sum(fdas_plan_t pl, const void* plane, const int64_t* 
   if (e != hipSuccess) return hip_fail(pl, e, "hipSetDevice");
   s = ensure_lengths(pl, lengths, n);
   if (s != FDAS_OK) return s;
+  if (!maxima_written(pl, plane))
+    return pl->fail(FDAS_ERR_STATE,
+                    "no column maxima were written for this plane buffer and batch (run the convolution or "
+                    "fdas_plane_maxima on it with this plan first)");
   const HarmArgs a = harm_args(pl, plane, cands, capacity, d_count);
   if ((e = launch_harmonic_sum(pl->p.plane_dtype, a, pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "harmonic sum");

@@ -129,3 +129,46 @@ def test_harmonic_sum_where_bounds_pass_everywhere_matches_oracle(lib, dt, nh):
         assert abs(float(g["power"]) - w.power) <= 1e-5 * w.power, cell
         assert g["r"] == np.float32(w.r) and g["z"] == np.float32(w.z), cell
     assert len(want) >= 30, len(want)
+
+
+def test_plane_maxima_and_harmonic_sum_argument_errors(lib):
+    """Host-side checks, nothing enqueued: fdas_plane_maxima refuses a plane
+    that is not 16-byte aligned or too small for the batch's values and
+    maxima; the harmonic sum refuses a plane buffer and batch for which the
+    plan wrote no maxima (values uploaded without fdas_plane_maxima, or a
+    batch other than the one convolved)."""
+    import ctypes
+    import torch
+    n = 1 << 17
+    say("column maxima argument errors")
+    pl = lib.Plan(store="bf16", plane="bf16", n_samples=n, max_batch_samples=2 * n, z_min=-16.0, z_max=16.0,
+                  z_step=2.0, n_harmonics=4, segment_len=1024)
+    lens1 = (ctypes.c_int64 * 1)(n)
+    need = pl.Z * (n // 2) * 9 // 8
+    buf = torch.full((need + 64,), 3.0, dtype=torch.bfloat16, device="cuda")
+    assert pl.lib.fdas_plane_maxima(pl.handle, ctypes.c_void_p(buf.data_ptr() + 2), lens1, 1, need * 2) == 1
+    assert b"16-byte" in pl.lib.fdas_last_error(pl.handle)
+    assert pl.lib.fdas_plane_maxima(pl.handle, ctypes.c_void_p(buf.data_ptr()), lens1, 1, need * 2 - 2) == 2
+    torch.cuda.synchronize()
+    assert bool((buf == 3.0).all())
+    # values uploaded, no maxima written: refused, count untouched
+    P = pl.new_plane(n // 2)
+    P.fill_(1.0)
+    count = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    cands = torch.zeros((16, 8), dtype=torch.int32, device="cuda")
+    st = pl.lib.fdas_harmonic_sum(pl.handle, ctypes.c_void_p(P.data_ptr()), lens1, 1, ctypes.c_void_p(cands.data_ptr()),
+                                  16, ctypes.c_void_p(count.data_ptr()))
+    assert st == 7 and b"column maxima" in pl.lib.fdas_last_error(pl.handle)
+    pl.plane_maxima(P, [n])
+    _, c2 = pl.harmonic_sum(P, [n], capacity=16)
+    assert int(c2.item()) == 0
+    # a two-series convolution, then a harmonic sum of the first series alone
+    x = torch.from_numpy(np.concatenate([synth.make_series(n, [], 4, 0), synth.make_series(n, [], 5, 0)])).to("cuda")
+    P2 = pl.convolve(x, [0, n], [n, n])
+    st = pl.lib.fdas_harmonic_sum(pl.handle, ctypes.c_void_p(P2.data_ptr()), lens1, 1, ctypes.c_void_p(cands.data_ptr()),
+                                  16, ctypes.c_void_p(count.data_ptr()))
+    assert st == 7
+    torch.cuda.synchronize()
+    assert int(count.item()) == 7
+    _, c3 = pl.harmonic_sum(P2, [n, n], capacity=1 << 12)
+    pl.check(c3, 1 << 12)
