@@ -733,19 +733,21 @@ fdas_status fdas_search_chunked(fdas_plan_t pl, const float* series, const int64
   // max_batch_samples (and the per-call series limit) and whose plane fits
   // plane_bytes; a series that fits neither alone is an error before any work
   const int64_t N = pl->p.n_samples;
-  const int64_t per_bin = plane_buffer_bytes(pl, 1);  // 9/8 of a value per column: a whole number of bytes per bin
   std::vector<std::pair<int32_t, int32_t>> chunks;
   for (int32_t i = 0; i < n;) {
-    int64_t samples = 0, bytes = 0;
+    int64_t samples = 0, bins = 0;
     int32_t j = i;
     while (j < n) {
       const int64_t len = lengths[j];
       if (!(len == N || len == N / 2 || len == N / 4) || len < (1 << 17))
         return pl->fail(FDAS_ERR_ARG, "series lengths must be n_samples, n_samples/2 or n_samples/4 (and >= 2^17)");
       if (offsets[j] < 0 || (offsets[j] & 1)) return pl->fail(FDAS_ERR_ARG, "series offsets must be even and non-negative");
-      if (samples + len > pl->max_batch || bytes + len / 2 * per_bin > plane_bytes || j - i >= pl->max_series) break;
+      // the chunk's plane buffer: its values and their column maxima
+      if (samples + len > pl->max_batch || plane_buffer_bytes(pl, bins + len / 2) > plane_bytes ||
+          j - i >= pl->max_series)
+        break;
       samples += len;
-      bytes += len / 2 * per_bin;
+      bins += len / 2;
       ++j;
     }
     if (j == i)
