@@ -97,6 +97,10 @@ __device__ __forceinline__ void group_max(uint32_t (&v)[P]) {
   step(std::integral_constant<int, 0xB1>{});  // quad_perm [1, 0, 3, 2]
   step(std::integral_constant<int, 0x4E>{});  // quad_perm [2, 3, 0, 1]
   if constexpr (G == 8) step(std::integral_constant<int, 0x114>{});  // row_shr:4
+  // every lane computes the last step (one DPP max) rather than only the
+  // storing lane (a DPP move, then a max in its branch)
+#pragma unroll
+  for (int c = 0; c < P; ++c) asm volatile("" : "+v"(v[c]));
 }
 
 // A bin's power and the half-bin power after it, as one store.
