@@ -21,8 +21,11 @@
 namespace fdas {
 
 
-// ln P(Gamma(h, 1) > s) = -s + ln sum_{k<h} s^k / k!, integer h.
-__device__ inline double log_tail_gamma(double s, int h) {
+// ln P(Gamma(h, 1) > s) = -s + ln sum_{k<h} s^k / k!, integer h.  Not
+// inlined: the harmonic sum calls it only for passing cells, and inline its
+// FP64 logarithm would raise the kernel's register count (and lower the
+// blocks per CU) for every cell.
+__device__ __noinline__ double log_tail_gamma(double s, int h) {
   double term = 1.0, sum = 1.0;
   for (int k = 1; k < h; ++k) {
     term *= s / k;
@@ -100,6 +103,12 @@ struct HarmTile {
 template <int PDT>
 struct HarmCfg {
   static constexpr int CW = 256;  // cells per tile = threads per block
+  // wavefronts per SIMD asked of the register allocation (64 VGPRs for
+  // eight): eight blocks of a 16-bit plane fit in LDS (15.7 KB each at
+  // H = 16), five of an FP32 plane.  At H = 16 the allocation then keeps two
+  // values in scratch memory once per tile; 7 blocks per CU (72 VGPRs) ran
+  // 3 % slower, 5 (87 VGPRs, with the Gamma tail inlined) 10 % slower.
+  static constexpr int WAVES = Store<PDT>::RBYTES == 2 ? 8 : 5;
   // Tile order: groups of GROUP bands (48 trials) are swept over all column
   // tiles, the bands of a group interleaved.  Bands that are close in z
   // share the rows of the low harmonics, and a sweep's working set then
@@ -252,7 +261,8 @@ __device__ __forceinline__ uint32_t ceil_bits16(float v) {
 }
 
 template <int PDT, int H>
-__global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
+__global__ __launch_bounds__(HarmCfg<PDT>::CW) __attribute__((amdgpu_waves_per_eu(HarmCfg<PDT>::WAVES)))
+void k_harmsum(HarmArgs a) {
   using PS = Store<PDT>;
   using RT = typename PS::real_t;
   constexpr int NST = ilog2(H) + 1;
@@ -406,10 +416,12 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
         },
         [&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          // a valid trial's row and a searched cell's bin are inside the plane
-          const int row = a.j0 + (kBand / H) * k * u + HT::rel(k, t, neg);
-          const int bin = k * (R0 / H) + (2 * k * tid + H) / (2 * H);
-          return raw(plane + ((int64_t)row * nb + bin));
+          // a valid trial's row and a searched cell's bin are inside the
+          // plane: the strip's first row and bin (uniform) plus a 32-bit
+          // byte offset (fewer than 16 rows of at most 2^23 columns)
+          const RT* base = plane + ((int64_t)(a.j0 + (kBand / H) * k * u) * nb + k * (R0 / H));
+          const uint32_t off = (uint32_t)(HT::rel(k, t, neg) * nb + (2 * k * tid + H) / (2 * H)) * (uint32_t)ES;
+          return raw(reinterpret_cast<const RT*>(reinterpret_cast<const char*>(base) + off));
         });
     stage_sums<PDT, H>(x, [&](int st, float v) { S[st] = v; });
     double best = 0.0;
@@ -431,8 +443,9 @@ __global__ __launch_bounds__(HarmCfg<PDT>::CW) void k_harmsum(HarmArgs a) {
       c.harm = hh;
       c.R = R;
       c.j = j;
-      c.r = (float)((double)R / (hh << a.res_shift));
-      c.z = (float)((a.z_min + a.z_step * j) / hh);
+      // division by the power of two hh 2^res_shift, exactly
+      c.r = ldexpf((float)R, -(bi + a.res_shift));
+      c.z = (float)ldexp(a.z_min + a.z_step * j, -bi);
       c.power = S[bi];
       c.sigma = 0.f;  // filled in by k_cand_sigma
       a.cands[slot] = c;
