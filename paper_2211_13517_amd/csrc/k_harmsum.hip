@@ -105,9 +105,8 @@ struct HarmCfg {
   static constexpr int CW = 256;  // cells per tile = threads per block
   // wavefronts per SIMD asked of the register allocation (64 VGPRs for
   // eight): eight blocks of a 16-bit plane fit in LDS (15.7 KB each at
-  // H = 16), five of an FP32 plane.  At H = 16 the allocation then keeps two
-  // values in scratch memory once per tile; 7 blocks per CU (72 VGPRs) ran
-  // 3 % slower, 5 (87 VGPRs, with the Gamma tail inlined) 10 % slower.
+  // H = 16), five of an FP32 plane.  7 blocks per CU (72 VGPRs) ran 3 %
+  // slower, 5 (87 VGPRs, with the Gamma tail inlined) 10 % slower.
   static constexpr int WAVES = Store<PDT>::RBYTES == 2 ? 8 : 5;
   // Tile order: groups of GROUP bands (48 trials) are swept over all column
   // tiles, the bands of a group interleaved.  Bands that are close in z
@@ -243,6 +242,68 @@ __device__ __forceinline__ unsigned long long pass_mask(const HarmVals<H>& x, co
   return m;
 }
 
+// 16-bit planes: the H values of a cell held as the H/2 pairs that the
+// stage sums add by two-term dot products (pair 0 = (H/2, H); at stage
+// st >= 2 the pairs (ka, ka + 2 step), ka = step (4i + 1), step = H / 2^st),
+// each pair in one register.  Over the 16 trials of a band, a value is read
+// from LDS only when its strip row changes, straight into its half of the
+// pair's register.
+template <int H>
+struct PairSlot {
+  static constexpr int step(int k) { return k & -k; }
+  static constexpr int stage(int k) { return ilog2(H) - ilog2(step(k)); }
+  static constexpr int index(int k) {
+    return k == H || k == H / 2 ? 0 : (1 << (stage(k) - 2)) + (k / step(k) - 1) / 4;
+  }
+  static constexpr int half(int k) { return k == H ? 1 : k == H / 2 ? 0 : ((k / step(k) - 1) / 2) & 1; }
+};
+
+template <int PDT, int H, bool NEG, typename HT>
+__device__ __forceinline__ void band_pairs(const char* lds, const int* boff, const float* thr, uint32_t thr0_bits,
+                                           int t_lo, int t_hi, unsigned long long* bal) {
+  typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+  constexpr int NST = ilog2(H) + 1;
+  us2 P[H / 2];
+  const uint32_t thr0_hi = thr0_bits << 16;
+  auto dot = [](us2 w, float acc) {
+    if constexpr (PDT == FDAS_BF16) {
+      typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+      return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf2, w), __builtin_bit_cast(bf2, 0x3f803f80u), acc,
+                                             false);
+    } else {
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, w), __builtin_bit_cast(h2, 0x3c003c00u), acc, false);
+    }
+  };
+  static_for<0, kBand>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    static_for<1, H + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int row = HT::rel(k, t, NEG);
+      if constexpr (t == 0 || row != HT::rel(k, t - 1, NEG)) {
+        const uint16_t v = *reinterpret_cast<const uint16_t*>(lds + boff[k - 1] + row * HT::pitch(k) * 2);
+        if constexpr (PairSlot<H>::half(k) == 0)
+          P[PairSlot<H>::index(k)].x = v;
+        else
+          P[PairSlot<H>::index(k)].y = v;
+      }
+    });
+    {
+      // stage 0 on the raw bits of harmonic H, the high half of pair 0
+      unsigned long long m = __builtin_amdgcn_ballot_w64(__builtin_bit_cast(uint32_t, P[0]) >= thr0_hi);
+      float s = dot(P[0], 0.f);
+      m |= __builtin_amdgcn_ballot_w64(s >= thr[1]);
+      static_for<2, NST>([&](auto sc) {
+        constexpr int st = decltype(sc)::value;
+        static_for<0, (1 << st) / 4>([&](auto ic) { s = dot(P[(1 << (st - 2)) + decltype(ic)::value], s); });
+        m |= __builtin_amdgcn_ballot_w64(s >= thr[st]);
+      });
+      // trials outside the band's valid range: computed, then dropped
+      bal[t] = (t >= t_lo && t < t_hi) ? m : 0ull;
+    }
+  });
+}
+
 // Smallest 16-bit pattern of the plane type whose value is >= v (v > 0, or +inf).
 template <int PDT>
 __device__ __forceinline__ uint32_t ceil_bits16(float v) {
@@ -369,6 +430,10 @@ void k_harmsum(HarmArgs a) {
         return HT::rel(k, t, NEG) * HT::pitch(k) * ES;
       };
     };
+    if constexpr (Store<PDT>::RBYTES == 2 && H > 1) {
+      band_pairs<PDT, H, NEG, HT>(lds, boff, thr, thr0_bits, t_lo, t_hi, bal);
+      return;
+    }
     // software pipeline: the LDS reads of trial t + 1 are issued before the
     // sums of trial t (every trial's reads stay inside the strips)
     HarmVals<H> cur = load_vals<PDT, H, H>(lds, boff, offs(std::integral_constant<int, 0>{}), none);
@@ -397,6 +462,10 @@ void k_harmsum(HarmArgs a) {
 #pragma unroll
   for (int t = 0; t < kBand; ++t) mask |= (uint32_t)((bal[t] >> lane) & 1ull) << t;
   const bool neg = u < 0;
+  // the lane's bin offsets of the upper harmonics are recomputed here from an
+  // opaque copy of tid, not kept alive from the set-up over the band
+  int tid_x = tid;
+  asm volatile("" : "+v"(tid_x));
   auto raw = [](const RT* p) -> uint32_t {
     if constexpr (ES == 4)
       return *reinterpret_cast<const uint32_t*>(p);
@@ -420,7 +489,7 @@ void k_harmsum(HarmArgs a) {
           // plane: the strip's first row and bin (uniform) plus a 32-bit
           // byte offset (fewer than 16 rows of at most 2^23 columns)
           const RT* base = plane + ((int64_t)(a.j0 + (kBand / H) * k * u) * nb + k * (R0 / H));
-          const uint32_t off = (uint32_t)(HT::rel(k, t, neg) * nb + (2 * k * tid + H) / (2 * H)) * (uint32_t)ES;
+          const uint32_t off = (uint32_t)(HT::rel(k, t, neg) * nb + (2 * k * tid_x + H) / (2 * H)) * (uint32_t)ES;
           return raw(reinterpret_cast<const RT*>(reinterpret_cast<const char*>(base) + off));
         });
     stage_sums<PDT, H>(x, [&](int st, float v) { S[st] = v; });
