@@ -551,6 +551,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   a.G = pl->G;
   a.U = pl->U;
   a.seg_margin = pl->seg_margin;
+  a.tbound = (float)(std::sqrt(2.0 * pl->hmax + 1.0) / pl->L);
   // The grid is exactly what is resident at once: tiles are dealt
   // round-robin, so a block that had to wait for a slot would finish last.
   const int per_block = conv_waves_per_block(pl->L);

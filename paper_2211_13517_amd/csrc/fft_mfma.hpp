@@ -1,0 +1,152 @@
+// 1024-point inverse DFT of one wavefront in FP16 on the matrix cores.
+//
+// The unnormalised inverse DFT y[k] = sum_n x[n] w^{nk}, w = exp(+2 pi i/1024),
+// is split as n = 64 c + l, l = 16 t + 4 q + j, k = n' + 16 ka + 256 kb:
+//   1. X1[k1][l] = sum_c x[64 c + l] w16^{c k1}  (64 DFTs of 16 points)
+//   2. X1[k1][l] *= w^{l k1}
+//   3. Y_j[ka][k1] = sum_{l'} X1[k1][4 l' + j] w16^{l' ka}, l' = 4 t + q
+//      (64 DFTs of 16 points), then Y_j *= w64^{j ka}
+//   4. y[k1 + 16 ka + 256 kb] = sum_j Y_j[ka][k1] w4^{j kb}  (radix 4, in lane)
+// Stages 1 and 3 are dense 16 x 16 complex contractions, written as real
+// products [re | im] x [[Re W, Im W], [-Im W, Re W]] with K = 32, each a
+// v_mfma_f32_16x16x32_f16 (FP16 operands, FP32 sums).  The MFMA operand
+// layout (A[i][k] in lane i + 16 (k/8), element k%8; B[k][j] in lane
+// j + 16 (k/8), element k%8; D[i][j] in lane j + 16 (i/4), element i%4)
+// makes the K index of both stages (q, element e) <-> (index q + 4 (e/2),
+// part e%2), so one pair of weight registers serves as stage 1's B operand
+// and stage 3's A operand.  Stage 1 takes its operand through one LDS
+// transpose (each lane writes its 16 points, each lane reads 4 x 16 bytes);
+// stage 3's operand is already where stage 1's results are.  Twiddles and
+// the radix-4 stage are FP32 vector arithmetic.
+//
+// Input: lane l (= 16 q + n) holds x[64 c + l] in v[c].  Output: y[e][kb] of
+// lane (q, n) is y[n + 64 q + 16 e + 256 kb].
+#pragma once
+#include "common.hpp"
+
+namespace fdas {
+namespace mf {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXStride = 80;   // bytes per lane row of the transpose buffer (64 + 16 pad)
+constexpr int kXBytes = 64 * kXStride;
+constexpr int kTw2Stride = 17;  // c32 per lane of the stage-2 twiddle table (16 + 1 pad)
+constexpr int kTw2Size = 64 * kTw2Stride;
+constexpr int kTw3Size = 4 * 12;
+
+__device__ __forceinline__ uint32_t pack_h2(float a, float b) {
+  const h2 r = {(_Float16)a, (_Float16)b};
+  return __builtin_bit_cast(uint32_t, r);
+}
+
+// Per-lane DFT-16 weights: w0 (real outputs) and w1 (imaginary outputs) for
+// lane (q, n), element e: index idx = q + 4 (e/2), part e%2, w = w16^{idx n}.
+struct Weights {
+  h8 w0, w1;
+};
+
+__device__ __forceinline__ Weights make_weights(int lane) {
+  const int q = lane >> 4, n = lane & 15;
+  Weights W;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int idx = q + 4 * (e >> 1);
+    double s, c;
+    sincospi(2.0 * (double)((idx * n) & 15) / 16.0, &s, &c);
+    W.w0[e] = (_Float16)(float)((e & 1) ? -s : c);
+    W.w1[e] = (_Float16)(float)((e & 1) ? c : s);
+  }
+  return W;
+}
+
+// Twiddle tables (FP64 phases, rounded once to FP32), filled by the block:
+//   tw2[l * kTw2Stride + 4 t + j] = w^{n (16 t + 4 q + j)}  for lane l = 16 q + n
+//   tw3[12 q + 4 (j - 1) + e]     = w64^{j (4 q + e)}       for j = 1..3
+__device__ __forceinline__ void fill_tables(c32* tw2, c32* tw3, int tid, int nthreads) {
+  for (int i = tid; i < 64 * 16; i += nthreads) {
+    const int l = i >> 4, tj = i & 15, q = l >> 4, n = l & 15;
+    const int e = (n * (16 * (tj >> 2) + 4 * q + (tj & 3))) & 1023;
+    double s, c;
+    sincospi(2.0 * (double)e / 1024.0, &s, &c);
+    tw2[l * kTw2Stride + tj] = {(float)c, (float)s};
+  }
+  for (int i = tid; i < kTw3Size; i += nthreads) {
+    const int q = i / 12, j = (i % 12) / 4 + 1, e = i % 4;
+    double s, c;
+    sincospi(2.0 * (double)((j * (4 * q + e)) & 63) / 64.0, &s, &c);
+    tw3[i] = {(float)c, (float)s};
+  }
+}
+
+__device__ __forceinline__ c32 cmul_f(c32 a, c32 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// xb: this wavefront's transpose buffer (kXBytes, 16-byte aligned).
+__device__ __forceinline__ void ifft1024(const c32 (&v)[16], c32 (&y)[4][4], char* xb, const c32* tw2,
+                                         const c32* tw3, const Weights& W, int lane) {
+  const int q = lane >> 4, n = lane & 15;
+  // stage 1 operands: lane l writes chunk g = {x[c] : c = g, g + 4, g + 8, g + 12}
+  {
+    char* wp = xb + lane * kXStride;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint4 ch;
+      ch.x = pack_h2(v[g].re, v[g].im);
+      ch.y = pack_h2(v[g + 4].re, v[g + 4].im);
+      ch.z = pack_h2(v[g + 8].re, v[g + 8].im);
+      ch.w = pack_h2(v[g + 12].re, v[g + 12].im);
+      *reinterpret_cast<uint4*>(wp + 16 * g) = ch;
+    }
+  }
+  wave_lds_fence();
+  f4 d0[4], d1[4];
+  {
+    const char* rp = xb + n * kXStride + 16 * q;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // instance l = 16 t + n of the stage-1 DFTs, elements c = q + 4 s
+      const h8 A = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(rp + 16 * kXStride * t));
+      const f4 z = {0.f, 0.f, 0.f, 0.f};
+      d0[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w0, z, 0, 0, 0);
+      d1[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w1, z, 0, 0, 0);
+    }
+  }
+  wave_lds_fence();
+  // d0[t][j] + i d1[t][j] = X1[k1 = n][l = 16 t + 4 q + j]; twiddle, then
+  // stage 3 for each j with operand elements t = 0..3
+  const c32* twl = tw2 + lane * kTw2Stride;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h8 B;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const c32 x = cmul_f({d0[t][j], d1[t][j]}, twl[4 * t + j]);
+      B[2 * t] = (_Float16)x.re;
+      B[2 * t + 1] = (_Float16)x.im;
+    }
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    const f4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.w0, B, z, 0, 0, 0);
+    const f4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.w1, B, z, 0, 0, 0);
+    // Y_j[ka = 4 q + e][k1 = n] = e0[e] + i e1[e]
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e][j] = {e0[e], e1[e]};
+  }
+  // twiddles w64^{j ka} and the radix-4 stage over j (w4 = +i)
+  const c32* t3 = tw3 + 12 * q;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const c32 z0 = y[e][0], z1 = cmul_f(y[e][1], t3[e]), z2 = cmul_f(y[e][2], t3[4 + e]),
+              z3 = cmul_f(y[e][3], t3[8 + e]);
+    const c32 a = {z0.re + z2.re, z0.im + z2.im}, b = {z0.re - z2.re, z0.im - z2.im};
+    const c32 c = {z1.re + z3.re, z1.im + z3.im}, d = {z1.re - z3.re, z1.im - z3.im};
+    y[e][0] = {a.re + c.re, a.im + c.im};
+    y[e][2] = {a.re - c.re, a.im - c.im};
+    y[e][1] = {b.re - d.im, b.im + d.re};  // b + i d
+    y[e][3] = {b.re + d.im, b.im - d.re};  // b - i d
+  }
+}
+
+}  // namespace mf
+}  // namespace fdas

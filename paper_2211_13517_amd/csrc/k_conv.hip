@@ -22,11 +22,13 @@
 //
 // Every FFT holds 16 points per thread.  L = 1024: one wavefront owns a tile
 // and exchanges through its private LDS buffer, so the four wavefronts of a
-// block never wait for each other.  L = 2048, 4096, 8192: a block of L/16
+// block never wait for each other; with a 16-bit plane its inverse FFTs run
+// in FP16 on the matrix cores (fft_mfma.hpp).  L = 2048, 4096, 8192: a block of L/16
 // threads (2, 4 or 8 wavefronts) owns a tile and synchronises.
 // Tiles are dealt round-robin to wavefronts (resp. blocks) of a grid sized to
 // the machine, so every unit runs the same number of tiles to within one.
 #include "fft.hpp"
+#include "fft_mfma.hpp"
 #include "launch.hpp"
 
 namespace fdas {
@@ -118,9 +120,26 @@ template <> struct PowerPair<FDAS_F16> {
   __device__ __forceinline__ static type pack(float p, float h) { return Store<FDAS_F16>::pack(c32{p, h}); }
 };
 
-template <class FS, int SDT, int PDT, bool BLOCK, bool IB>
+// The 1024-point inverse FFTs of a 16-bit plane (one wavefront per tile,
+// radix 16, no half-bin outputs) run their two DFT-16 stages in FP16 on the
+// matrix cores (fft_mfma.hpp).  The operands are scaled per tile by a power
+// of two: with |F| <= f and |T_j| <= tbound, every product is at most 2^10
+// and every stage-1 result at most 2^14 in magnitude, inside FP16's range,
+// and the power is scaled back exactly.
+template <int L, int R, int PDT, bool IB>
+constexpr bool use_mfma() {
+  return L == 1024 && R == 16 && !IB && Store<PDT>::RBYTES == 2;
+}
+
+struct MfCtx {
+  const c32* tw2;
+  const c32* tw3;
+  mf::Weights W;
+};
+
+template <class FS, int SDT, int PDT, bool BLOCK, bool IB, bool MF = false>
 __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* xb, const c32* tw, int tid,
-                                          c32* edge) {
+                                          c32* edge, const MfCtx* mc = nullptr) {
   using SS = Store<SDT>;
   using PS = Store<PDT>;
   using CT = typename SS::cplx_t;
@@ -145,6 +164,25 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
     F[c] = {in ? val.re : 0.f, in ? val.im : 0.f};
   });
   fft_run<FS, -1, BLOCK>(F, xb, tw, tid);
+  float pscale = 1.f;  // FP16 path: factor that undoes the tile's scaling on the power
+  if constexpr (MF) {
+    float fm = 0.f;
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      fm = fmaxf(fm, fmaxf(fabsf(F[c].re), fabsf(F[c].im)));
+    });
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) fm = fmaxf(fm, __shfl_xor(fm, o, 64));
+    int e;
+    frexpf(fm * 1.41421356f * a.tbound, &e);  // every product |F T_j| < 2^e
+    e = min(max(e, -100), 100);
+    const float sc = ldexpf(1.f, 10 - e);
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      F[c] = {F[c].re * sc, F[c].im * sc};
+    });
+    pscale = ldexpf(1.f, 2 * (e - 10));
+  }
 
   const CT* T = reinterpret_cast<const CT*>(a.tspec);
   RT* out = reinterpret_cast<RT*>(a.plane) + d.plane_off;
@@ -176,6 +214,30 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
       constexpr int c = decltype(cc)::value;
       v[c] = cmul(F[c], SS::unpack(tc[c]));
     });
+    if constexpr (MF) {
+      // output y[e][kb] of lane (q, n) is FFT index n + 64 q + 16 e + 256 kb
+      c32 y[4][4];
+      mf::ifft1024(v, y, reinterpret_cast<char*>(xb), mc->tw2, mc->tw3, mc->W, tid);
+      const int q = tid >> 4, n = tid & 15;
+      RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + n + 64 * q);
+      RT* mdst = mx + (size_t)t * (uint32_t)(d.nbins / G8) + (r0 + (n & ~(G8 - 1)) + 64 * q) / G8;
+      RT p[16];
+      uint32_t m[16];
+      static_for<0, 16>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        p[i] = PS::pack_real(cnorm(y[i / 4][i % 4]) * pscale);
+        m[i] = capped_bits<PDT>(p[i]);
+      });
+      group_max<G8>(m);
+      static_for<0, 16>([&](auto ic) {
+        constexpr int i = decltype(ic)::value, off = 16 * (i / 4) + 256 * (i % 4);
+        const int k = n + 64 * q + off;
+        if (k >= lo && k < hi) {
+          dst[off] = p[i];
+          if (lead) mdst[off / G8] = from_bits<PDT>(m[i]);
+        }
+      });
+    } else {
     fft_run<FS, 1, BLOCK>(v, xb, tw, tid);
     if constexpr (IB) {
       c32 nx[P];
@@ -229,6 +291,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
         }
       });
     }
+    }
     static_for<0, P>([&](auto cc) { tc[decltype(cc)::value] = tn[decltype(cc)::value]; });
   }
 }
@@ -243,21 +306,34 @@ constexpr int kConvWaves = 4;  // wavefronts per block of the one-wavefront-per-
 template <int L, int R = 16>
 using ConvShape = FftShape<L, 16, R>;
 
-// Two wavefronts per SIMD: with the template prefetch in registers a third
-// wavefront (possible for 16-bit storage) measured no faster.
+// Wavefronts per SIMD: two for the FP32 inverse FFTs (with the template
+// prefetch in registers a third measured no faster); three for the FP16
+// matrix-core inverse FFT with 16-bit storage (168 VGPRs, 52 KB of LDS per
+// block), whose chain of dependent steps per template (LDS transpose, MFMA,
+// twiddles, MFMA) needs the extra wavefront to hide its latency (-5 %).
+template <int L, int R, int SDT, int PDT, bool IB>
+constexpr int conv_wave_occupancy() { return use_mfma<L, R, PDT, IB>() && Store<SDT>::RBYTES == 2 ? 3 : 2; }
+
 template <int L, int SDT, int PDT, bool IB, int R>
-__global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(64 * kConvWaves) __attribute__((amdgpu_waves_per_eu(conv_wave_occupancy<L, R, SDT, PDT, IB>())))
 void k_conv_wave(ConvArgs a) {
   using FS = ConvShape<L, R>;
   static_assert(FS::NT == 64, "one wavefront per FFT");
+  constexpr bool MF = use_mfma<L, R, PDT, IB>();
+  static_assert(!MF || FS::XBUF * sizeof(c32) >= mf::kXBytes, "transpose buffer");
   __shared__ c32 tw[FS::TW_SIZE];
-  __shared__ c32 xb[kConvWaves][FS::XBUF];
+  __shared__ __align__(16) c32 xb[kConvWaves][FS::XBUF];
+  __shared__ c32 tw2[MF ? mf::kTw2Size : 1];
+  __shared__ c32 tw3[MF ? mf::kTw3Size : 1];
   stage_table(tw, a.tw, FS::TW_SIZE);
+  if constexpr (MF) mf::fill_tables(tw2, tw3, threadIdx.x, blockDim.x);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * kConvWaves;
+  MfCtx mc;
+  if constexpr (MF) mc = {tw2, tw3, mf::make_weights(lane)};
   for (int64_t tile = (int64_t)blockIdx.x * kConvWaves + wave; tile < a.n_tiles; tile += nw)
-    conv_tile<FS, SDT, PDT, false, IB>(a, tile, xb[wave], tw, lane, nullptr);
+    conv_tile<FS, SDT, PDT, false, IB, MF>(a, tile, xb[wave], tw, lane, nullptr, &mc);
 }
 
 template <int L, int SDT, int PDT, bool IB>

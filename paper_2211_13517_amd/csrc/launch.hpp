@@ -73,6 +73,9 @@ struct ConvArgs {
   // seg_margin: FFT index of a segment's first output (>= h_max; it and U
   // are multiples of the bins per column maximum)
   int32_t n_series, Z, G, U, seg_margin;
+  // bound on |T_j[k]| of the template spectra, sqrt(2 h_max + 1) / L (unit-energy
+  // taps, the inverse FFT's 1/L folded in): sets the FP16 inverse FFT's scaling
+  float tbound;
 };
 // interbin: also write the half-bin power between each output and the next
 // R: radix of the convolution FFT's passes (16; 8 or 4 at L = 1024)
