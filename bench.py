@@ -6,7 +6,9 @@ power plane, harmonic sums up to 16 and the 6-sigma threshold.  The series is
 N = 2^23 float32 samples (536.9 s at 64 us) with 8 injected accelerated
 sinusoids, already resident in HBM.  Throughput is bins x templates per second
 (N/2 * 193 per step).  The headline path stores spectrum, templates and plane
-in bfloat16 (FP32 arithmetic); the FP32-storage path is timed beside it.
+in bfloat16; its arithmetic is FP32, except the two DFT-16 stages of each
+1024-point inverse FFT, which run as FP16 matrix-core products with FP32 sums
+(dtype "f32+f16"); the FP32-storage path (all FP32) is timed beside it.
 
 Prints one JSON line.  Extra legs: the FP64 oracle timed on a bounded sample
 of the same workload on the host's cores (cpu_baseline, the only use of the
@@ -732,7 +734,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        # FP16 matrix-core DFT stages on the 1024-point, 16-bit-plane path
+        "dtype": "f32+f16" if (L == 1024 and plane_dt != "f32" and not args.interbin) else "f32",
         "data": "synthetic",
         "config": {"workload": f"SKA-like single series: N=2^{int(math.log2(n))} float32, 8 injected accelerated "
                                f"sinusoids, 193 templates z in [-96,96] step 1, segment {L}, median normalisation, "

@@ -5,8 +5,10 @@
  * correlates the spectrum of each dedispersed time series with templates of
  * constant acceleration, so the cost grows linearly with the number of
  * acceleration trials; section 2.2 ("Mixed-Precision") performs that
- * correlation in the frequency domain with FFTs, stores the data of this
- * convolution stage in bfloat16 and keeps the arithmetic in FP32; section 3
+ * correlation in the frequency domain with FFTs and converts this
+ * convolution stage to bfloat16 (here: its data stored in 16 bits, its
+ * arithmetic FP32 apart from the FP16 matrix-core stages described at
+ * fdas_convolve_spectrum); section 3
  * ("Results") sets the SKA-like workload (600 s at 64 us, 5925 DM trials of
  * which 3050 at full time resolution, 193 acceleration trials).  The
  * harmonic-summing stage that follows the correlation is cited in the
@@ -181,8 +183,15 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
                           const int64_t *lengths_host, int32_t n_series, void *spectrum_out);
 
 /* Convolution (section 2.2: the correlation with every template runs in the
- * frequency domain through FFTs, this stage's data stored in store_dtype and
- * its arithmetic in FP32; section 2.1: one output row per acceleration trial).
+ * frequency domain through FFTs, this stage's data stored in store_dtype;
+ * section 2.1: one output row per acceleration trial).  Arithmetic is FP32,
+ * except with a 16-bit plane_dtype at L = 1024 (fft_radix 16, no interbin):
+ * there the two 16-point DFT stages of each 1024-point inverse FFT are FP16
+ * matrix-core products with FP32 sums, the products with the templates are
+ * FP16 (templates rounded once from FP64 to FP16, times 2^10), and every
+ * segment's operands are scaled by a power of two that keeps them inside
+ * FP16's range (undone exactly on the power); the error this adds to an
+ * output is about 2^-11 of the segment's rms amplitude.
  * From a normalised spectrum (store_dtype, packed): overlap-save
  * segments of L bins starting at s U - h' (zero outside [0, N/2); h' and U
  * as at fdas_plan), one forward FFT per segment, then for every template j:

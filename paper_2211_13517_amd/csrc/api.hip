@@ -77,7 +77,8 @@ struct fdas_plan_s {
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   int64_t off_status = 0, off_tw[kNumFftSizes] = {}, off_exptab = 0, off_taps = 0, off_tspec = 0, off_desc = 0,
-          off_lists = 0, off_Y = 0, off_Zb = 0, off_spec = 0, off_tw_conv = 0, total = 0;
+          off_lists = 0, off_Y = 0, off_Zb = 0, off_spec = 0, off_tw_conv = 0, off_tspec16 = 0, total = 0;
+  bool mfma = false;  // inverse FFTs in FP16 on the matrix cores (FP16 template copy in the workspace)
   bool templates_ready = false;
   std::string err;
   // current batch
@@ -246,6 +247,9 @@ fdas_status fdas_plan(const fdas_params* params, int device, void* hip_stream, f
   o = align256(o + (int64_t)Z * pl->K * 16);
   pl->off_tspec = o;
   o = align256(o + (int64_t)Z * L * cbytes(p.store_dtype));
+  pl->mfma = conv_uses_mfma(L, radix, p.plane_dtype, p.interbin != 0);
+  pl->off_tspec16 = o;
+  o = align256(o + (pl->mfma ? (int64_t)Z * L * 4 : 0));
   pl->off_desc = o;
   o = align256(o + (int64_t)pl->max_series * (int64_t)sizeof(SeriesDesc));
   pl->off_lists = o;
@@ -333,6 +337,9 @@ fdas_status fdas_make_templates(fdas_plan_t pl) {
   if ((e = launch_template_spectra(pl->p.store_dtype, taps, tab, pl->Z, pl->hmax, pl->L, pl->ws + pl->off_tspec,
                                    pl->stream)) != hipSuccess)
     return hip_fail(pl, e, "template spectra");
+  if (pl->mfma && (e = launch_template_spectra(FDAS_F16, taps, tab, pl->Z, pl->hmax, pl->L, pl->ws + pl->off_tspec16,
+                                               pl->stream, kTspec16Shift)) != hipSuccess)
+    return hip_fail(pl, e, "template spectra (FP16)");
   pl->templates_ready = true;
   return FDAS_OK;
 }
@@ -541,6 +548,7 @@ static fdas_status run_conv(fdas_plan_t pl, const void* spec, void* plane, int64
   ConvArgs a;
   a.spec = spec;
   a.tspec = pl->ws + pl->off_tspec;
+  a.tspec16 = pl->ws + pl->off_tspec16;
   a.plane = plane;
   a.maxima = plane_maxima(pl, plane);
   a.desc = reinterpret_cast<const SeriesDesc*>(pl->ws + pl->off_desc);

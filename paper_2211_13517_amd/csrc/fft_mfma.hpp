@@ -14,12 +14,12 @@
 // j + 16 (k/8), element k%8; D[i][j] in lane j + 16 (i/4), element i%4)
 // makes the K index of both stages (q, element e) <-> (index q + 4 (e/2),
 // part e%2), so one pair of weight registers serves as stage 1's B operand
-// and stage 3's A operand.  Stage 1 takes its operand through one LDS
-// transpose (each lane writes its 16 points, each lane reads 4 x 16 bytes);
-// stage 3's operand is already where stage 1's results are.  Twiddles and
-// the radix-4 stage are FP32 vector arithmetic.
+// and stage 3's A operand.  Stage 1 takes its operand through a transpose
+// across the four 16-lane rows in registers (v_permlane32_swap, then
+// v_permlane16_swap); stage 3's operand is already where stage 1's results
+// are.  Twiddles and the radix-4 stage are FP32 vector arithmetic.
 //
-// Input: lane l (= 16 q + n) holds x[64 c + l] in v[c].  Output: y[e][kb] of
+// Input: lane l (= 16 q + n) holds x[64 c + l] in h[c] (an FP16 pair).  Output: y[e][kb] of
 // lane (q, n) is y[n + 64 q + 16 e + 256 kb].
 #pragma once
 #include "common.hpp"
@@ -31,8 +31,6 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kXStride = 80;   // bytes per lane row of the transpose buffer (64 + 16 pad)
-constexpr int kXBytes = 64 * kXStride;
 constexpr int kTw2Stride = 17;  // c32 per lane of the stage-2 twiddle table (16 + 1 pad)
 constexpr int kTw2Size = 64 * kTw2Stride;
 constexpr int kTw3Size = 4 * 12;
@@ -83,37 +81,51 @@ __device__ __forceinline__ void fill_tables(c32* tw2, c32* tw3, int tid, int nth
 
 __device__ __forceinline__ c32 cmul_f(c32 a, c32 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
-// xb: this wavefront's transpose buffer (kXBytes, 16-byte aligned).
-__device__ __forceinline__ void ifft1024(const c32 (&v)[16], c32 (&y)[4][4], char* xb, const c32* tw2,
-                                         const c32* tw3, const Weights& W, int lane) {
+// Complex product of FP16 pairs (real part in the low half) by two packed
+// FP16 operations: (fr tr, fr ti), then + (-fi ti, fi tr).
+__device__ __forceinline__ uint32_t cmul_h2(uint32_t f, uint32_t t) {
+  const h2 a = __builtin_bit_cast(h2, f), b = __builtin_bit_cast(h2, t);
+  const h2 p = h2{a.x, a.x} * b;
+  const h2 r = __builtin_elementwise_fma(h2{-a.y, a.y}, h2{b.y, b.x}, p);
+  return __builtin_bit_cast(uint32_t, r);
+}
+
+// x: the 16 input points of this lane as FP16 pairs (overwritten).
+__device__ __forceinline__ void ifft1024(uint32_t (&h)[16], c32 (&y)[4][4], const c32* tw2, const c32* tw3,
+                                         const Weights& W, int lane) {
   const int q = lane >> 4, n = lane & 15;
-  // stage 1 operands: lane l writes chunk g = {x[c] : c = g, g + 4, g + 8, g + 12}
-  {
-    char* wp = xb + lane * kXStride;
+  // stage 1 operands: chunk g of a lane is {x[c] : c = g, g + 4, g + 8, g + 12}
+  // as FP16 pairs; lane (q, n) needs chunk q of lane (t, n) for t = 0..3, a
+  // 4 x 4 transpose of (row, chunk) in each column n: rows 0-1 <-> 2-3 for
+  // chunks (0, 2) and (1, 3), then rows 0 <-> 1 and 2 <-> 3 for chunks
+  // (0, 1) and (2, 3), after which chunk t of lane (q, n) is chunk q of lane
+  // (t, n)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      uint4 ch;
-      ch.x = pack_h2(v[g].re, v[g].im);
-      ch.y = pack_h2(v[g + 4].re, v[g + 4].im);
-      ch.z = pack_h2(v[g + 8].re, v[g + 8].im);
-      ch.w = pack_h2(v[g + 12].re, v[g + 12].im);
-      *reinterpret_cast<uint4*>(wp + 16 * g) = ch;
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const auto r = __builtin_amdgcn_permlane32_swap(h[g + 4 * s], h[g + 2 + 4 * s], false, false);
+      h[g + 4 * s] = r[0];
+      h[g + 2 + 4 * s] = r[1];
     }
-  }
-  wave_lds_fence();
+#pragma unroll
+  for (int g = 0; g < 4; g += 2)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const auto r = __builtin_amdgcn_permlane16_swap(h[g + 4 * s], h[g + 1 + 4 * s], false, false);
+      h[g + 4 * s] = r[0];
+      h[g + 1 + 4 * s] = r[1];
+    }
   f4 d0[4], d1[4];
-  {
-    const char* rp = xb + n * kXStride + 16 * q;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      // instance l = 16 t + n of the stage-1 DFTs, elements c = q + 4 s
-      const h8 A = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(rp + 16 * kXStride * t));
-      const f4 z = {0.f, 0.f, 0.f, 0.f};
-      d0[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w0, z, 0, 0, 0);
-      d1[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w1, z, 0, 0, 0);
-    }
+  for (int t = 0; t < 4; ++t) {
+    // instance l = 16 t + n of the stage-1 DFTs, elements c = q + 4 s
+    const uint4 ch = {h[t], h[t + 4], h[t + 8], h[t + 12]};
+    const h8 A = __builtin_bit_cast(h8, ch);
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    d0[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w0, z, 0, 0, 0);
+    d1[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w1, z, 0, 0, 0);
   }
-  wave_lds_fence();
   // d0[t][j] + i d1[t][j] = X1[k1 = n][l = 16 t + 4 q + j]; twiddle, then
   // stage 3 for each j with operand elements t = 0..3
   const c32* twl = tw2 + lane * kTw2Stride;

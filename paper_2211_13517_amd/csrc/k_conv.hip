@@ -165,6 +165,7 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
   });
   fft_run<FS, -1, BLOCK>(F, xb, tw, tid);
   float pscale = 1.f;  // FP16 path: factor that undoes the tile's scaling on the power
+  uint32_t Fh[MF ? P : 1];  // FP16 path: the scaled segment spectrum as FP16 pairs
   if constexpr (MF) {
     float fm = 0.f;
     static_for<0, P>([&](auto cc) {
@@ -173,15 +174,16 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
     });
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) fm = fmaxf(fm, __shfl_xor(fm, o, 64));
+    // the FP16 templates are T_j 2^10: every product |F T_j 2^10| < 2^e
     int e;
-    frexpf(fm * 1.41421356f * a.tbound, &e);  // every product |F T_j| < 2^e
-    e = min(max(e, -100), 100);
+    frexpf(fm * 1.41421356f * ldexpf(a.tbound, kTspec16Shift), &e);
+    e = min(max(e, -60), 60);
     const float sc = ldexpf(1.f, 10 - e);
     static_for<0, P>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      F[c] = {F[c].re * sc, F[c].im * sc};
+      Fh[c] = mf::pack_h2(F[c].re * sc, F[c].im * sc);
     });
-    pscale = ldexpf(1.f, 2 * (e - 10));
+    pscale = ldexpf(1.f, 2 * (e - 10 - kTspec16Shift));
   }
 
   const CT* T = reinterpret_cast<const CT*>(a.tspec);
@@ -195,29 +197,32 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
   constexpr int G8 = IB ? kPlaneMaxCols / 2 : kPlaneMaxCols;
   const int grp0 = tid & ~(G8 - 1);           // first lane of this lane's group
   const bool lead = (tid & (G8 - 1)) == G8 / 2;  // the lane that stores the group's maximum
-  const uint32_t toff = (uint32_t)tid * sizeof(CT);
-  CT tc[P];
+  // template spectra: the stored bank, or its FP16 copy (times 2^10) on the FP16 path
+  using TT = std::conditional_t<MF, uint32_t, CT>;
+  const TT* TB = reinterpret_cast<const TT*>(MF ? a.tspec16 : a.tspec);
+  const uint32_t toff = (uint32_t)tid * sizeof(TT);
+  TT tc[P];
   static_for<0, P>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    tc[c] = ld_off<CT>(T + (size_t)t0 * L, toff + c * NT * sizeof(CT));
+    tc[c] = ld_off<TT>(TB + (size_t)t0 * L, toff + c * NT * sizeof(TT));
   });
   for (int t = t0; t < t1; ++t) {
     // prefetch the next template while this one is transformed
-    const CT* Tn = T + (size_t)min(t + 1, t1 - 1) * L;
-    CT tn[P];
+    const TT* Tn = TB + (size_t)min(t + 1, t1 - 1) * L;
+    TT tn[P];
     static_for<0, P>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      tn[c] = ld_off<CT>(Tn, toff + c * NT * sizeof(CT));
-    });
-    c32 v[P];
-    static_for<0, P>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      v[c] = cmul(F[c], SS::unpack(tc[c]));
+      tn[c] = ld_off<TT>(Tn, toff + c * NT * sizeof(TT));
     });
     if constexpr (MF) {
+      uint32_t h[P];
+      static_for<0, P>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        h[c] = mf::cmul_h2(Fh[c], tc[c]);
+      });
       // output y[e][kb] of lane (q, n) is FFT index n + 64 q + 16 e + 256 kb
       c32 y[4][4];
-      mf::ifft1024(v, y, reinterpret_cast<char*>(xb), mc->tw2, mc->tw3, mc->W, tid);
+      mf::ifft1024(h, y, mc->tw2, mc->tw3, mc->W, tid);
       const int q = tid >> 4, n = tid & 15;
       RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + n + 64 * q);
       RT* mdst = mx + (size_t)t * (uint32_t)(d.nbins / G8) + (r0 + (n & ~(G8 - 1)) + 64 * q) / G8;
@@ -238,6 +243,11 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
         }
       });
     } else {
+    c32 v[P];
+    static_for<0, P>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      v[c] = cmul(F[c], SS::unpack(tc[c]));
+    });
     fft_run<FS, 1, BLOCK>(v, xb, tw, tid);
     if constexpr (IB) {
       c32 nx[P];
@@ -309,8 +319,8 @@ using ConvShape = FftShape<L, 16, R>;
 // Wavefronts per SIMD: two for the FP32 inverse FFTs (with the template
 // prefetch in registers a third measured no faster); three for the FP16
 // matrix-core inverse FFT with 16-bit storage (168 VGPRs, 52 KB of LDS per
-// block), whose chain of dependent steps per template (LDS transpose, MFMA,
-// twiddles, MFMA) needs the extra wavefront to hide its latency (-5 %).
+// block), whose chain of dependent steps per template (register transpose,
+// MFMA, twiddles, MFMA) needs the extra wavefront to hide its latency (-5 %).
 template <int L, int R, int SDT, int PDT, bool IB>
 constexpr int conv_wave_occupancy() { return use_mfma<L, R, PDT, IB>() && Store<SDT>::RBYTES == 2 ? 3 : 2; }
 
@@ -320,9 +330,8 @@ void k_conv_wave(ConvArgs a) {
   using FS = ConvShape<L, R>;
   static_assert(FS::NT == 64, "one wavefront per FFT");
   constexpr bool MF = use_mfma<L, R, PDT, IB>();
-  static_assert(!MF || FS::XBUF * sizeof(c32) >= mf::kXBytes, "transpose buffer");
   __shared__ c32 tw[FS::TW_SIZE];
-  __shared__ __align__(16) c32 xb[kConvWaves][FS::XBUF];
+  __shared__ c32 xb[kConvWaves][FS::XBUF];
   __shared__ c32 tw2[MF ? mf::kTw2Size : 1];
   __shared__ c32 tw3[MF ? mf::kTw3Size : 1];
   stage_table(tw, a.tw, FS::TW_SIZE);
@@ -347,6 +356,14 @@ __global__ __launch_bounds__(ConvShape<L>::NT) __attribute__((amdgpu_waves_per_e
   for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x)
     conv_tile<FS, SDT, PDT, true, IB>(a, tile, xb, tw, threadIdx.x, edge);
 }
+
+bool conv_uses_mfma(int L, int R, int pdt, bool interbin) {
+  return L == 1024 && R == 16 && !interbin && (pdt == FDAS_BF16 || pdt == FDAS_F16);
+}
+static_assert(use_mfma<1024, 16, FDAS_BF16, false>() && use_mfma<1024, 16, FDAS_F16, false>() &&
+                  !use_mfma<1024, 16, FDAS_F32, false>() && !use_mfma<1024, 16, FDAS_BF16, true>() &&
+                  !use_mfma<1024, 8, FDAS_BF16, false>() && !use_mfma<2048, 16, FDAS_BF16, false>(),
+              "conv_uses_mfma matches use_mfma");
 
 int conv_waves_per_block(int L) { return L == 1024 ? kConvWaves : L / 16 / 64; }
 

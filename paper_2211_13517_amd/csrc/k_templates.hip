@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_template_taps(double z_min, double z_st
 
 template <int SDT>
 __global__ __launch_bounds__(256) void k_template_spectra(const c64* __restrict__ taps, const c64* __restrict__ tab,
-                                                          int hmax, int L, void* out) {
+                                                          int hmax, int L, void* out, int shift) {
   using SS = Store<SDT>;
   const int j = blockIdx.y;
   const int k = blockIdx.x * 256 + threadIdx.x;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_template_spectra(const c64* __restrict_
     const int idx = (int)(((int64_t)k * q) & (int64_t)(L - 1));  // L is a power of two
     acc = c64add(acc, c64mul(t, tab[idx]));
   }
-  const double s = 1.0 / (double)L;
+  const double s = ldexp(1.0, shift) / (double)L;
   typename SS::cplx_t* o = reinterpret_cast<typename SS::cplx_t*>(out) + (size_t)j * L;
   o[k] = SS::pack(c32{(float)(acc.re * s), (float)(acc.im * s)});
 }
@@ -82,12 +82,12 @@ hipError_t launch_template_taps(double z_min, double z_step, int Z, int margin, 
 }
 
 hipError_t launch_template_spectra(int sdt, const c64* taps, const c64* tab, int Z, int hmax, int L, void* out,
-                                   hipStream_t st) {
+                                   hipStream_t st, int shift) {
   const dim3 g((L + 255) / 256, Z);
   switch (sdt) {
-    case FDAS_F32: hipLaunchKernelGGL((k_template_spectra<FDAS_F32>), g, dim3(256), 0, st, taps, tab, hmax, L, out); break;
-    case FDAS_BF16: hipLaunchKernelGGL((k_template_spectra<FDAS_BF16>), g, dim3(256), 0, st, taps, tab, hmax, L, out); break;
-    case FDAS_F16: hipLaunchKernelGGL((k_template_spectra<FDAS_F16>), g, dim3(256), 0, st, taps, tab, hmax, L, out); break;
+    case FDAS_F32: hipLaunchKernelGGL((k_template_spectra<FDAS_F32>), g, dim3(256), 0, st, taps, tab, hmax, L, out, shift); break;
+    case FDAS_BF16: hipLaunchKernelGGL((k_template_spectra<FDAS_BF16>), g, dim3(256), 0, st, taps, tab, hmax, L, out, shift); break;
+    case FDAS_F16: hipLaunchKernelGGL((k_template_spectra<FDAS_F16>), g, dim3(256), 0, st, taps, tab, hmax, L, out, shift); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

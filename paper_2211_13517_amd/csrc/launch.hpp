@@ -53,8 +53,9 @@ hipError_t launch_unpack_normalise(int sdt, int M, int B, int mode, double var_s
 hipError_t launch_exp_table(int L, c64* tab, hipStream_t st);
 hipError_t launch_template_taps(double z_min, double z_step, int Z, int margin, int hmax, c64* taps,
                                 hipStream_t st);
+// out[j][k] = T_j[k] 2^shift in dtype sdt (shift = 0 for the stored bank)
 hipError_t launch_template_spectra(int sdt, const c64* taps, const c64* tab, int Z, int hmax, int L, void* out,
-                                   hipStream_t st);
+                                   hipStream_t st, int shift = 0);
 
 // Column maxima: a plane buffer holds the batch's plane values, then for
 // every row of every series the maximum of each run of kPlaneMaxCols columns
@@ -65,6 +66,7 @@ constexpr int kPlaneMaxCols = 8;
 struct ConvArgs {
   const void* spec;        // packed normalised spectrum, store dtype
   const void* tspec;       // template spectra [Z][L], store dtype
+  const void* tspec16;     // FP16 matrix-core path: the spectra times 2^10 as FP16 pairs
   void* plane;             // packed planes, plane dtype
   void* maxima;            // their column maxima, plane dtype
   const SeriesDesc* desc;  // per series
@@ -81,6 +83,9 @@ struct ConvArgs {
 // R: radix of the convolution FFT's passes (16; 8 or 4 at L = 1024)
 hipError_t launch_conv(int L, int R, int sdt, int pdt, bool interbin, const ConvArgs& a, int grid, hipStream_t st);
 int conv_waves_per_block(int L);
+// whether the convolution's inverse FFTs run in FP16 on the matrix cores
+bool conv_uses_mfma(int L, int R, int pdt, bool interbin);
+constexpr int kTspec16Shift = 10;  // FP16 template spectra are stored times 2^10
 int conv_blocks_per_cu(int L, int R, int sdt, int pdt, bool interbin);  // resident blocks per CU (occupancy query)
 bool conv_radix_supported(int L, int R);
 int conv_twiddle_size(int L, int R);           // entries of the convolution FFT's twiddle table
