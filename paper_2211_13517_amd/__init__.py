@@ -165,9 +165,15 @@ class Plan:
         self._check(self.lib.fdas_query(h, byref(ws), byref(L), byref(hmax), byref(Z)))
         self.ws_bytes, self.L, self.hmax, self.Z = ws.value, L.value, hmax.value, Z.value
         # columns per bin of the plane: 2 on a half-bin (interbinned) plane,
-        # which also gives up one output per segment
+        # which also gives up one output per segment.  Segment geometry as
+        # fdas_plan sets it: the first output seg_margin = h_max rounded up to
+        # a multiple of the bins per column maximum (8, or 4 on a half-bin
+        # plane) into the FFT, U outputs, the largest such multiple with
+        # U <= L - 2 seg_margin (- 1 on a half-bin plane)
         self.res = 2 if p.interbin else 1
-        self.U = self.L - 2 * self.hmax - (1 if p.interbin else 0)
+        run = 8 // self.res
+        self.seg_margin = -(-self.hmax // run) * run
+        self.U = (self.L - 2 * self.seg_margin - (1 if p.interbin else 0)) // run * run
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self._check(self.lib.fdas_set_workspace(h, c_void_p(self.workspace.data_ptr()), self.ws_bytes))
         self.store_dtype, self.plane_dtype = p.store_dtype, p.plane_dtype

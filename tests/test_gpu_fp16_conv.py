@@ -1,0 +1,87 @@
+"""GPU: the 1024-point convolution of a 16-bit plane, whose inverse FFTs run
+their two 16-point DFT stages in FP16 on the matrix cores (FP16 products with
+the templates, FP32 sums, operands scaled per segment by a power of two),
+against the oracle's FP64 plane, every cell.
+
+Tolerance, from that arithmetic.  Each FP16 rounding of an operand x_n
+(half an ulp, 2^-11 relative at most) adds to an output y_k = sum_n x_n w^nk
+an error whose size is set by sum_n |x_n|^2 = mean_k |y_k|^2 (Parseval), so
+the error of every output of a segment is a small multiple of 2^-11 A, with
+A^2 the mean power over the segment's L outputs: about 2^-10.5 A rms for the
+five roundings on the path (segment spectrum, template, product, stage-1
+result, DFT weights).  With D = 2^-7 A (twice a five-sigma tail) and the
+16-bit storage of the power (2^-9 relative; 2^-7 allowed),
+    |P_gpu - P| <= 2^-7 max(P, 1) + 2 sqrt(P) D + D^2.
+A 16-bit spectrum (store dtype) adds its own rounding, |dA| <= u |A| with
+u = 2^-9 (BF16) or 2^-11 (FP16): by Cauchy-Schwarz over the unit-energy taps
+the output moves by at most u sqrt(E_r), E_r = sum_{|q| <= h_max} |A_{r+q}|^2,
+which joins D.  A weak cell in a segment that holds a very strong signal
+therefore carries an error set by that signal, not by its own power;
+detections keep the 3 % bound of the 16-bit path.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fdas64 as o
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def window_energy(a, h):
+    """E_r = sum_{|q| <= h} |a_{r+q}|^2 (zero outside the spectrum)."""
+    c = np.concatenate([[0.0], np.cumsum(np.abs(a) ** 2)])
+    r = np.arange(len(a))
+    return c[np.minimum(r + h + 1, len(a))] - c[np.maximum(r - h, 0)]
+
+
+def segment_rms(ref, L, U, h):
+    """sqrt of the mean power over each segment's L outputs, per cell."""
+    Z, nb = ref.shape
+    A = np.empty_like(ref)
+    for s in range((nb + U - 1) // U):
+        a0, a1 = max(s * U - h, 0), min(s * U - h + L, nb)
+        A[:, s * U:min((s + 1) * U, nb)] = np.sqrt(ref[:, a0:a1].mean(axis=1))[:, None]
+    return A
+
+
+@pytest.mark.parametrize("store,plane,strong", [("bf16", "bf16", False), ("f16", "f16", False),
+                                                ("bf16", "bf16", True), ("f32", "bf16", True)])
+def test_fp16_matrix_core_plane_matches_oracle(lib, store, plane, strong):
+    """N = 2^17, 17 templates, L = 1024: the small case (one injection of
+    peak power ~ 80), and the same series with two more tones of peak power
+    ~ 4e4 and ~ 8e3 (strong).  Every cell within the bound above; cells at
+    or above the single-harmonic threshold within 3 %; without strong tones
+    also every cell within the 16-bit path's flat 5e-2 max(P, 1)."""
+    import torch
+    x, inj, _ = synth.small_case(seed=1)
+    n = len(x)
+    if strong:
+        extra = [synth.Injection(2.0, 21000.5, 6.0, 0.3), synth.Injection(0.5, 40000.0, -10.0, 1.1)]
+        x = (x.astype(np.float64) + sum(synth.chirp(n, i) for i in extra)).astype(np.float32)
+    say("FP16 matrix-core convolution", store, plane, "strong tones" if strong else "small case")
+    pl = lib.Plan(store=store, plane=plane, n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, n_harmonics=4,
+                  segment_len=1024)
+    P = pl.convolve(torch.from_numpy(x).to("cuda"), [0], [n])
+    zs = o.z_grid(-16, 16, 2)
+    a = o.normalise(o.spectrum(x), "median")
+    ref = o.power_plane(a, zs)
+    got = P.float().cpu().numpy().astype(np.float64).reshape(pl.Z, -1)
+    err = np.abs(got - ref)
+    A = segment_rms(ref, pl.L, pl.U, pl.seg_margin)
+    u = {"f32": 0.0, "bf16": 2.0 ** -9, "f16": 2.0 ** -11}[store]
+    D = 2.0 ** -7 * A + u * np.sqrt(window_energy(a, pl.hmax))[None, :]
+    bound = 2.0 ** -7 * np.maximum(ref, 1.0) + 2.0 * np.sqrt(ref) * D + D * D
+    bad = err > bound
+    assert not bad.any(), (np.argwhere(bad)[:5], float((err / bound).max()))
+    det = ref >= o.threshold(1)
+    assert det.any()
+    assert float((err[det] / ref[det]).max()) < 3e-2
+    if strong:
+        assert ref.max() > 3e4  # a tone ~1000 times the single-harmonic threshold
+    else:
+        assert np.all(err < 5e-2 * np.maximum(ref, 1.0)), float((err / np.maximum(ref, 1.0)).max())

@@ -35,12 +35,13 @@ def convolve(lib, x, params, store="f32", plane="f32"):
 
 @pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
 def test_interbin_plane_fp32_full_parity(lib, L):
-    """Every column of a 2^17-sample series (U = L - 2 h_max - 1: 68 to 9
+    """Every column of a 2^17-sample series (h' = h_max rounded up to a
+    multiple of 4, U the largest multiple of 4 <= L - 2 h' - 1: 68 to 9
     segments with a ragged tail), the one-wavefront and the block tiles."""
     x, inj, _ = synth.small_case(seed=1)
     say("fdas_convolve interbin f32 small case", L)
     pl, got = convolve(lib, x, small_params(L))
-    assert pl.U == L - 2 * pl.hmax - 1
+    assert pl.seg_margin == 24 and pl.U == (L - 49) // 4 * 4
     zs = o.z_grid(-16, 16, 2)
     ref = o.interbin_plane(o.normalise(o.spectrum(x), "median"), zs)
     bad = np.abs(got - ref) > 1e-4 * np.maximum(ref, 1.0)
