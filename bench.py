@@ -72,7 +72,7 @@ def parse():
     return ap.parse_args()
 
 
-SOURCES = {"conv": ("k_conv.hip", "fft.hpp", "common.hpp", "launch.hpp"),
+SOURCES = {"conv": ("k_conv.hip", "fft.hpp", "fft_mfma.hpp", "common.hpp", "launch.hpp"),
            "harmonic_sum": ("k_harmsum.hip", "fft.hpp", "common.hpp", "launch.hpp")}
 
 
