@@ -735,7 +735,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # FP16 matrix-core DFT stages on the 1024-point, 16-bit-plane path
-        "dtype": "f32+f16" if (L == 1024 and plane_dt != "f32" and not args.interbin) else "f32",
+        "dtype": "f32+f16" if (L == 1024 and plane_dt != "f32") else "f32",
         "data": "synthetic",
         "config": {"workload": f"SKA-like single series: N=2^{int(math.log2(n))} float32, 8 injected accelerated "
                                f"sinusoids, 193 templates z in [-96,96] step 1, segment {L}, median normalisation, "

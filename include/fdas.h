@@ -185,7 +185,7 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
 /* Convolution (section 2.2: the correlation with every template runs in the
  * frequency domain through FFTs, this stage's data stored in store_dtype;
  * section 2.1: one output row per acceleration trial).  Arithmetic is FP32,
- * except with a 16-bit plane_dtype at L = 1024 (fft_radix 16, no interbin):
+ * except with a 16-bit plane_dtype at L = 1024 (fft_radix 16; bins or half bins):
  * there the two 16-point DFT stages of each 1024-point inverse FFT are FP16
  * matrix-core products with FP32 sums, the products with the templates are
  * FP16 (templates rounded once from FP64 to FP16, times 2^10), and every

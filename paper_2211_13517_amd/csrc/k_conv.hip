@@ -121,14 +121,14 @@ template <> struct PowerPair<FDAS_F16> {
 };
 
 // The 1024-point inverse FFTs of a 16-bit plane (one wavefront per tile,
-// radix 16, no half-bin outputs) run their two DFT-16 stages in FP16 on the
+// radix 16, bins or half bins) run their two DFT-16 stages in FP16 on the
 // matrix cores (fft_mfma.hpp).  The operands are scaled per tile by a power
 // of two: with |F| <= f and |T_j| <= tbound, every product is at most 2^10
 // and every stage-1 result at most 2^14 in magnitude, inside FP16's range,
 // and the power is scaled back exactly.
 template <int L, int R, int PDT, bool IB>
 constexpr bool use_mfma() {
-  return L == 1024 && R == 16 && !IB && Store<PDT>::RBYTES == 2;
+  return L == 1024 && R == 16 && Store<PDT>::RBYTES == 2;
 }
 
 struct MfCtx {
@@ -224,24 +224,77 @@ __device__ __forceinline__ void conv_tile(const ConvArgs& a, int64_t tile, c32* 
       c32 y[4][4];
       mf::ifft1024(h, y, mc->tw2, mc->tw3, mc->W, tid);
       const int q = tid >> 4, n = tid & 15;
-      RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + n + 64 * q);
       RT* mdst = mx + (size_t)t * (uint32_t)(d.nbins / G8) + (r0 + (n & ~(G8 - 1)) + 64 * q) / G8;
-      RT p[16];
       uint32_t m[16];
-      static_for<0, 16>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        p[i] = PS::pack_real(cnorm(y[i / 4][i % 4]) * pscale);
-        m[i] = capped_bits<PDT>(p[i]);
-      });
-      group_max<G8>(m);
-      static_for<0, 16>([&](auto ic) {
-        constexpr int i = decltype(ic)::value, off = 16 * (i / 4) + 256 * (i % 4);
-        const int k = n + 64 * q + off;
-        if (k >= lo && k < hi) {
-          dst[off] = p[i];
-          if (lead) mdst[off / G8] = from_bits<PDT>(m[i]);
-        }
-      });
+      if constexpr (IB) {
+        // successor y[k + 1] of output k: the next lane of the row (DPP
+        // row_shl:1); for the row's last lane, lane 0 of the row in the next
+        // register (row_shr:15, the other lanes keeping theirs), or for the
+        // last register (e = 3) lane 0 of the next row (a shuffle; lane 63
+        // takes lane 0's register of the next kb)
+        auto shl1 = [](float v) {
+          return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, true));
+        };
+        auto from_row0 = [](float old, float v) {
+          return __int_as_float(
+              __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x11F, 0xF, 0xF, false));
+        };
+        c32 nx[4][4];
+        static_for<0, 4>([&](auto kc) {
+          constexpr int kb = decltype(kc)::value;
+          static_for<0, 3>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            nx[e][kb] = {from_row0(shl1(y[e][kb].re), y[e + 1][kb].re), from_row0(shl1(y[e][kb].im), y[e + 1][kb].im)};
+          });
+          c32 o = y[0][kb];
+          if constexpr (kb < 3) {
+            if (tid == 0) o = y[0][kb + 1];
+          } else {
+            if (tid == 0) o = {0.f, 0.f};
+          }
+          const int src = (tid + 1) & 63;
+          const c32 w = {__shfl(o.re, src, 64), __shfl(o.im, src, 64)};
+          const c32 sl = {shl1(y[3][kb].re), shl1(y[3][kb].im)};
+          nx[3][kb] = n == 15 ? w : sl;
+        });
+        using PP = PowerPair<PDT>;
+        typename PP::type* dst =
+            reinterpret_cast<typename PP::type*>(out + (size_t)t * (2u * (uint32_t)d.nbins)) + (r0 + n + 64 * q);
+        float p[16], hh[16];
+        static_for<0, 16>([&](auto ic) {
+          constexpr int i = decltype(ic)::value, e = i / 4, kb = i % 4;
+          const c32 dv = {y[e][kb].re - nx[e][kb].re, y[e][kb].im - nx[e][kb].im};
+          p[i] = cnorm(y[e][kb]) * pscale;
+          hh[i] = 0.5f * cnorm(dv) * pscale;
+          m[i] = max(capped_bits<PDT>(PS::pack_real(p[i])), capped_bits<PDT>(PS::pack_real(hh[i])));
+        });
+        group_max<G8>(m);
+        static_for<0, 16>([&](auto ic) {
+          constexpr int i = decltype(ic)::value, off = 16 * (i / 4) + 256 * (i % 4);
+          const int k = n + 64 * q + off;
+          if (k >= lo && k < hi) {
+            dst[off] = PP::pack(p[i], hh[i]);
+            if (lead) mdst[off / G8] = from_bits<PDT>(m[i]);
+          }
+        });
+      } else {
+        RT* dst = out + (size_t)t * (uint32_t)d.nbins + (r0 + n + 64 * q);
+        RT p[16];
+        static_for<0, 16>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          p[i] = PS::pack_real(cnorm(y[i / 4][i % 4]) * pscale);
+          m[i] = capped_bits<PDT>(p[i]);
+        });
+        group_max<G8>(m);
+        static_for<0, 16>([&](auto ic) {
+          constexpr int i = decltype(ic)::value, off = 16 * (i / 4) + 256 * (i % 4);
+          const int k = n + 64 * q + off;
+          if (k >= lo && k < hi) {
+            dst[off] = p[i];
+            if (lead) mdst[off / G8] = from_bits<PDT>(m[i]);
+          }
+        });
+      }
     } else {
     c32 v[P];
     static_for<0, P>([&](auto cc) {
@@ -357,11 +410,11 @@ __global__ __launch_bounds__(ConvShape<L>::NT) __attribute__((amdgpu_waves_per_e
     conv_tile<FS, SDT, PDT, true, IB>(a, tile, xb, tw, threadIdx.x, edge);
 }
 
-bool conv_uses_mfma(int L, int R, int pdt, bool interbin) {
-  return L == 1024 && R == 16 && !interbin && (pdt == FDAS_BF16 || pdt == FDAS_F16);
+bool conv_uses_mfma(int L, int R, int pdt, bool) {
+  return L == 1024 && R == 16 && (pdt == FDAS_BF16 || pdt == FDAS_F16);
 }
 static_assert(use_mfma<1024, 16, FDAS_BF16, false>() && use_mfma<1024, 16, FDAS_F16, false>() &&
-                  !use_mfma<1024, 16, FDAS_F32, false>() && !use_mfma<1024, 16, FDAS_BF16, true>() &&
+                  use_mfma<1024, 16, FDAS_BF16, true>() && !use_mfma<1024, 16, FDAS_F32, false>() &&
                   !use_mfma<1024, 8, FDAS_BF16, false>() && !use_mfma<2048, 16, FDAS_BF16, false>(),
               "conv_uses_mfma matches use_mfma");
 
