@@ -17,7 +17,9 @@
 // and stage 3's A operand.  Stage 1 takes its operand through a transpose
 // across the four 16-lane rows in registers (v_permlane32_swap, then
 // v_permlane16_swap); stage 3's operand is already where stage 1's results
-// are.  Twiddles and the radix-4 stage are FP32 vector arithmetic.
+// are.  Stage 1's results are rounded to FP16 pairs and twiddled in packed
+// FP16 (v_pk_mul_f16, v_pk_fma_f16, FP16 table); the last twiddles and the
+// radix-4 stage are FP32 vector arithmetic.
 //
 // Input: lane l (= 16 q + n) holds x[64 c + l] in h[c] (an FP16 pair).  Output: y[e][kb] of
 // lane (q, n) is y[n + 64 q + 16 e + 256 kb].
@@ -31,13 +33,15 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTw2Stride = 17;  // c32 per lane of the stage-2 twiddle table (16 + 1 pad)
+constexpr int kTw2Stride = 20;  // FP16 pairs per lane of the stage-2 twiddle table (16 + 4 pad)
 constexpr int kTw2Size = 64 * kTw2Stride;
 constexpr int kTw3Size = 4 * 12;
 
+// Two floats as an FP16 pair (round to nearest even), one v_cvt_pk_f16_f32.
 __device__ __forceinline__ uint32_t pack_h2(float a, float b) {
-  const h2 r = {(_Float16)a, (_Float16)b};
-  return __builtin_bit_cast(uint32_t, r);
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2));
 }
 
 // Per-lane DFT-16 weights: w0 (real outputs) and w1 (imaginary outputs) for
@@ -60,16 +64,16 @@ __device__ __forceinline__ Weights make_weights(int lane) {
   return W;
 }
 
-// Twiddle tables (FP64 phases, rounded once to FP32), filled by the block:
-//   tw2[l * kTw2Stride + 4 t + j] = w^{n (16 t + 4 q + j)}  for lane l = 16 q + n
-//   tw3[12 q + 4 (j - 1) + e]     = w64^{j (4 q + e)}       for j = 1..3
-__device__ __forceinline__ void fill_tables(c32* tw2, c32* tw3, int tid, int nthreads) {
+// Twiddle tables (FP64 phases, rounded once), filled by the block:
+//   tw2[l * kTw2Stride + 4 j + t] = w^{n (16 t + 4 q + j)}  for lane l = 16 q + n (FP16 pairs)
+//   tw3[12 q + 4 (j - 1) + e]     = w64^{j (4 q + e)}       for j = 1..3 (FP32)
+__device__ __forceinline__ void fill_tables(uint32_t* tw2, c32* tw3, int tid, int nthreads) {
   for (int i = tid; i < 64 * 16; i += nthreads) {
-    const int l = i >> 4, tj = i & 15, q = l >> 4, n = l & 15;
-    const int e = (n * (16 * (tj >> 2) + 4 * q + (tj & 3))) & 1023;
+    const int l = i >> 4, jt = i & 15, q = l >> 4, n = l & 15, j = jt >> 2, t = jt & 3;
+    const int e = (n * (16 * t + 4 * q + j)) & 1023;
     double s, c;
     sincospi(2.0 * (double)e / 1024.0, &s, &c);
-    tw2[l * kTw2Stride + tj] = {(float)c, (float)s};
+    tw2[l * kTw2Stride + jt] = pack_h2((float)c, (float)s);
   }
   for (int i = tid; i < kTw3Size; i += nthreads) {
     const int q = i / 12, j = (i % 12) / 4 + 1, e = i % 4;
@@ -91,7 +95,7 @@ __device__ __forceinline__ uint32_t cmul_h2(uint32_t f, uint32_t t) {
 }
 
 // x: the 16 input points of this lane as FP16 pairs (overwritten).
-__device__ __forceinline__ void ifft1024(uint32_t (&h)[16], c32 (&y)[4][4], const c32* tw2, const c32* tw3,
+__device__ __forceinline__ void ifft1024(uint32_t (&h)[16], c32 (&y)[4][4], const uint32_t* tw2, const c32* tw3,
                                          const Weights& W, int lane) {
   const int q = lane >> 4, n = lane & 15;
   // stage 1 operands: chunk g of a lane is {x[c] : c = g, g + 4, g + 8, g + 12}
@@ -126,18 +130,19 @@ __device__ __forceinline__ void ifft1024(uint32_t (&h)[16], c32 (&y)[4][4], cons
     d0[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w0, z, 0, 0, 0);
     d1[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, W.w1, z, 0, 0, 0);
   }
-  // d0[t][j] + i d1[t][j] = X1[k1 = n][l = 16 t + 4 q + j]; twiddle, then
-  // stage 3 for each j with operand elements t = 0..3
-  const c32* twl = tw2 + lane * kTw2Stride;
+  // d0[t][j] + i d1[t][j] = X1[k1 = n][l = 16 t + 4 q + j]; FP16 pairs,
+  // twiddled in packed FP16, are stage 3's operand for each j (elements
+  // t = 0..3)
+  const uint4* twl = reinterpret_cast<const uint4*>(tw2 + lane * kTw2Stride);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    h8 B;
+    const uint4 tj = twl[j];
+    const uint32_t tt[4] = {tj.x, tj.y, tj.z, tj.w};
+    uint4 b;
+    uint32_t* bb = &b.x;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const c32 x = cmul_f({d0[t][j], d1[t][j]}, twl[4 * t + j]);
-      B[2 * t] = (_Float16)x.re;
-      B[2 * t + 1] = (_Float16)x.im;
-    }
+    for (int t = 0; t < 4; ++t) bb[t] = cmul_h2(pack_h2(d0[t][j], d1[t][j]), tt[t]);
+    const h8 B = __builtin_bit_cast(h8, b);
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     const f4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.w0, B, z, 0, 0, 0);
     const f4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.w1, B, z, 0, 0, 0);

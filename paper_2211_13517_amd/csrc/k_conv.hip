@@ -132,7 +132,7 @@ constexpr bool use_mfma() {
 }
 
 struct MfCtx {
-  const c32* tw2;
+  const uint32_t* tw2;
   const c32* tw3;
   mf::Weights W;
 };
@@ -385,7 +385,7 @@ void k_conv_wave(ConvArgs a) {
   constexpr bool MF = use_mfma<L, R, PDT, IB>();
   __shared__ c32 tw[FS::TW_SIZE];
   __shared__ c32 xb[kConvWaves][FS::XBUF];
-  __shared__ c32 tw2[MF ? mf::kTw2Size : 1];
+  __shared__ __align__(16) uint32_t tw2[MF ? mf::kTw2Size : 1];
   __shared__ c32 tw3[MF ? mf::kTw3Size : 1];
   stage_table(tw, a.tw, FS::TW_SIZE);
   if constexpr (MF) mf::fill_tables(tw2, tw3, threadIdx.x, blockDim.x);
