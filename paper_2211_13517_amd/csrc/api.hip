@@ -372,17 +372,22 @@ static fdas_status set_batch(fdas_plan_t pl, const int64_t* offsets, const int64
   if (pl->p.templates_per_tile > 0) {
     G = (pl->Z + pl->p.templates_per_tile - 1) / pl->p.templates_per_tile;
   } else {
-    // W tile owners take tiles round-robin, so with T = nseg * G tiles the
-    // launch lasts ceil(T/W) rounds of one tile (Z/G inverse FFTs plus the
-    // segment's forward FFT): choose the G that minimises that product.
+    // A tile costs Z/G inverse FFTs plus its segment's forward FFT.  The
+    // T = nseg * G tiles are dealt evenly over the CUs, and the tile owners
+    // resident on one CU (waves, or blocks for the multi-wave FFTs) share its
+    // throughput, so a CU with T_cu tiles and S owners takes about
+    // max(1, T_cu / S) tile times: choose the G that minimises that.  (A
+    // model by rounds of the slowest owner over-weights a partial last round
+    // and picked groups of ~28 templates, 5 % slower at N = 2^23 than the
+    // 65-193 this one picks.)
     const int per_cu = std::max(1, conv_blocks_per_cu(pl->L, pl->p.fft_radix, pl->p.store_dtype, pl->p.plane_dtype,
                                                       pl->p.interbin != 0));
-    const int64_t W = (int64_t)pl->cu_count * per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
+    const double S = (double)per_cu * (pl->L == 1024 ? conv_waves_per_block(pl->L) : 1);
     double best = 1e300;
     G = 1;
     for (int g = 1; g <= pl->Z; ++g) {
-      const double rounds = std::ceil((double)nseg_total * g / (double)W);
-      const double t = rounds * ((double)pl->Z / g + 1.0);
+      const double t_cu = std::ceil((double)nseg_total * g / (double)pl->cu_count);
+      const double t = std::max(1.0, t_cu / S) * ((double)pl->Z / g + 1.0);
       if (t < best - 1e-9) {
         best = t;
         G = g;
