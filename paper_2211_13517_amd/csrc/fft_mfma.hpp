@@ -1,4 +1,7 @@
-// 1024-point inverse DFT of one wavefront in FP16 on the matrix cores.
+// 1024-point inverse DFT of one wavefront in FP16 on the matrix cores: the
+// inverse FFT of the frequency-domain correlation (section 2.2) with its
+// dense stages in 16-bit arithmetic, as that section converts the
+// convolution stage to a 16-bit format.
 //
 // The unnormalised inverse DFT y[k] = sum_n x[n] w^{nk}, w = exp(+2 pi i/1024),
 // is split as n = 64 c + l, l = 16 t + 4 q + j, k = n' + 16 ka + 256 kb:
