@@ -142,3 +142,26 @@ def test_fp16_matrix_core_half_bin_plane_matches_oracle(lib, strong):
     bound = np.empty_like(ref)
     bound[:, 0::2], bound[:, 1::2] = bb, bh
     check_detections(err, ref, bound, strong, res=2)
+
+
+@pytest.mark.parametrize("store,plane,interbin", [("bf16", "bf16", 0), ("bf16", "bf16", 1), ("f32", "f32", 0)])
+def test_plane_does_not_depend_on_template_grouping(lib, store, plane, interbin):
+    """The templates a wavefront runs per loaded segment (automatic, all 17,
+    5, 1) change which wavefront computes an output, never its arithmetic:
+    the planes and their column maxima are bit-identical."""
+    import torch
+    x, inj, _ = synth.small_case(seed=1)
+    n = len(x)
+    xt = torch.from_numpy(x).to("cuda")
+    say("template grouping invariance", store, plane, interbin)
+    ref = None
+    for tpt in (0, 17, 5, 1):
+        pl = lib.Plan(store=store, plane=plane, n_samples=n, z_min=-16.0, z_max=16.0, z_step=2.0, n_harmonics=4,
+                      segment_len=1024, interbin=interbin, templates_per_tile=tpt)
+        P = pl.convolve(xt, [0], [n])
+        got = (P.view(torch.int16 if P.element_size() == 2 else torch.int32).cpu().numpy().copy(),
+               pl.maxima(P).view(torch.int16 if P.element_size() == 2 else torch.int32).cpu().numpy().copy())
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), tpt
