@@ -34,7 +34,10 @@
  *    independent of each other.
  *  - Complex values are (re, im) pairs of the storage type: FDAS_F32 8 bytes,
  *    FDAS_BF16 and FDAS_F16 4 bytes (re in the low half), rounded to nearest
- *    even on conversion.
+ *    even on conversion.  FDAS_F16 holds magnitudes up to 65504: a spectrum
+ *    component or a power above that is stored as +inf (a power plane of
+ *    median-normalised noise has mean 1; a signal saturates an FP16 plane
+ *    only above ~65000 times the noise power, where FDAS_BF16 does not).
  *  - Batches: series are float32, given by device pointer `series` plus host
  *    arrays offsets[i] (first sample of series i in `series`) and lengths[i]
  *    (its length N_i: n_samples, n_samples/2 or n_samples/4, i.e. full
