@@ -360,6 +360,10 @@ void k_harmsum(HarmArgs a) {
   // every item is loaded without bounds tests.
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
   const bool interior = t_lo == 0 && t_hi == kBand && R0 + 2 * CW <= nb;
+  // interior tiles (every strip row and column inside the plane) copy with
+  // no bounds tests: a uniform branch between two instances of the copy
+  auto copy = [&](auto intc) {
+  constexpr bool INTERIOR = decltype(intc)::value;
   static_for<1, H + 1>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int NCH = HT::chunks(k), ITEMS = HT::rows(k) * NCH;
@@ -377,14 +381,20 @@ void k_harmsum(HarmArgs a) {
       if (f0 + wave0 >= ITEMS) continue;  // wave-uniform
       const int f = f0 + tid;
       const int r = div_small<NCH>(f), c = f - (int)__umul24(r, NCH);
-      const bool inside = (unsigned)(base + r) < (unsigned)a.Z && c0 + c * CH < len;
-      if (f < ITEMS && (interior || inside)) {
+      bool ok = f < ITEMS;
+      if constexpr (!INTERIOR) ok = ok && (unsigned)(base + r) < (unsigned)a.Z && c0 + c * CH < len;
+      if (ok) {
         uint32_t e = __umul24(r, len) + c * CH;  // element offset (< 2^27)
         asm volatile("" : "+v"(e));              // (keeps the 24-bit multiply)
         load_lds16(src + e * ES, reinterpret_cast<char*>(strip) + HT::off(k) * ES + (f0 + wave0) * 16);
       }
     }
   });
+  };
+  if (interior)
+    copy(std::true_type{});
+  else
+    copy(std::false_type{});
   __syncthreads();
 
   const int R = R0 + tid;
