@@ -220,8 +220,25 @@ class EnergyMeter:
             raise RuntimeError(f"no unique amdsmi device for pci {want} among {len(handles)}")
 
     def joules(self) -> float:
+        return self.read()[0]
+
+    def read(self):
+        """(joules, the counter's own timestamp in seconds, or None if it
+        reports none).  The counter advances in steps (about once a second on
+        MI355X), and its timestamp moves with each step."""
         e = self.smi.amdsmi_get_energy_count(self.h)
-        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+        ts = e.get("timestamp") or 0
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6, (ts * 1e-9 if ts else None)
+
+    @staticmethod
+    def power(r0, r1, wall_s):
+        """Mean power between two reads: energy over the counter's own time
+        between its updates (a window of wall time would see one, two or
+        three one-second steps of the counter), else over the wall time."""
+        (e0, ts0), (e1, ts1) = r0, r1
+        if ts0 is not None and ts1 is not None and ts1 > ts0:
+            return (e1 - e0) / (ts1 - ts0)
+        return (e1 - e0) / wall_s
 
     def gfxclk_mhz(self):
         """Graphics clock from the metrics table: the average if reported,
@@ -247,19 +264,22 @@ class EnergyMeter:
 
 def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=3):
     """Energy per 10^12 bins x templates of the whole step for each storage
-    type, from the energy counter over about `seconds` of back-to-back steps.
-    Each window is preceded by `preroll` seconds of the same steps, so that a
-    counter that lags the load still sees only that load inside the window;
-    the storage types alternate `reps` times and the median window is
-    reported (a window whose counter reading glitches does not move it).
-    The idle power is taken over one second after a second of rest.  Clocks
-    are whatever the GPU runs at (reported, not set)."""
+    type: the mean power over a window of about `seconds` of back-to-back
+    steps (energy over the counter's own time between its updates, so that
+    the counter's one-second steps do not alias with the window) times the
+    window's wall time per step.  Each window is preceded by `preroll`
+    seconds of the same steps, so that the counter interval that reaches back
+    before the window still sees only that load; the storage types alternate
+    `reps` times and the median window is reported.  The idle power is taken
+    over two seconds after a second of rest.  Clocks are whatever the GPU
+    runs at (reported, not set)."""
     torch.cuda.synchronize()
     time.sleep(1.0)
-    e0, t0 = meter.joules(), time.perf_counter()
-    time.sleep(1.0)
-    e1, t1 = meter.joules(), time.perf_counter()
-    idle = (e1 - e0) / (t1 - t0)
+    r0, t0 = meter.read(), time.perf_counter()
+    for _ in range(2):
+        time.sleep(1.0)
+    r1, t1 = meter.read(), time.perf_counter()
+    idle = meter.power(r0, r1, t1 - t0)
     out = {"idle_W": idle, "device": meter.matched, "clock_control": "none (default clocks)"}
     acc = {name: {"E": 0.0, "T": 0.0, "steps": 0, "J_per_1e12_bt_each": [], "ms_per_step_each": [], "W_each": []}
            for name in runs}
@@ -269,18 +289,19 @@ def energy_leg(torch, meter, runs, bt, seconds=2.0, preroll=3.0, reps=3):
                 r["step"]()
             torch.cuda.synchronize()  # the window must not inherit queued pre-roll work
             k = max(20, int(seconds / r["step_s"]))
-            e0, t0 = meter.joules(), time.perf_counter()
+            r0, t0 = meter.read(), time.perf_counter()
             for _ in range(k):
                 r["step"]()
             torch.cuda.synchronize()
-            e1, t1 = meter.joules(), time.perf_counter()
+            r1, t1 = meter.read(), time.perf_counter()
+            w = meter.power(r0, r1, t1 - t0)
             a = acc[name]
-            a["E"] += e1 - e0
+            a["E"] += w * (t1 - t0)
             a["T"] += t1 - t0
             a["steps"] += k
-            a["J_per_1e12_bt_each"].append((e1 - e0) / (k * bt) * 1e12)
+            a["J_per_1e12_bt_each"].append(w * (t1 - t0) / (k * bt) * 1e12)
             a["ms_per_step_each"].append((t1 - t0) / k * 1e3)
-            a["W_each"].append((e1 - e0) / (t1 - t0))
+            a["W_each"].append(w)
     for name, a in acc.items():
         j = float(np.median(a["J_per_1e12_bt_each"]))
         w = float(np.median(a["W_each"]))

@@ -159,3 +159,51 @@ def test_energy_leg_median_ignores_one_glitched_window(monkeypatch):
     assert min(each) < 0.9 * max(each)                         # the glitch is visible
     assert out["bf16"]["avg_W"] == pytest.approx(600.0, rel=1e-3)
     assert out["bf16"]["J_per_1e12_bt"] == pytest.approx(0.6 * 1e-3 / 1e9 * 1e12 * 1000, rel=1e-3)
+
+
+def test_energy_leg_uses_the_counters_own_time_between_its_steps(monkeypatch):
+    """A counter that advances only once per second (with its timestamp, as
+    MI355X's does) makes a 2-second window see one, two or three steps; the
+    power taken over the counter's own time between its steps is the true
+    power in every window, and so is the energy per work."""
+    clock = {"t": 0.0}
+    true = {"acc": 0.0}
+    smi = FakeSmi(["0000:75:00.0"], resolution=1.0)
+    state = {"acc": 0.0, "ts": 0.0}
+
+    def stepped(h):
+        k = int(clock["t"])                      # the counter's last update, at a whole second
+        if k > state["ts"]:
+            # energy up to the update instant: the true accumulator then
+            state["acc"], state["ts"] = energy_at(k), float(k)
+        return {"energy_accumulator": int(round(state["acc"] * 1e6)), "counter_resolution": 1.0,
+                "timestamp": int(state["ts"] * 1e9)}
+
+    hist = [(0.0, 0.0)]
+
+    def energy_at(t):
+        # linear interpolation of the true accumulator at time t
+        for (t0, a0), (t1, a1) in zip(hist, hist[1:]):
+            if t0 <= t <= t1:
+                return a0 + (a1 - a0) * (t - t0) / (t1 - t0) if t1 > t0 else a1
+        return hist[-1][1]
+
+    def advance(seconds, watts):
+        clock["t"] += seconds
+        true["acc"] += watts * seconds
+        hist.append((clock["t"], true["acc"]))
+
+    smi.amdsmi_get_energy_count = stepped
+    meter = bench.EnergyMeter(fake_torch(), smi=smi)
+    monkeypatch.setattr(bench.time, "sleep", lambda s: advance(s, 100.0))
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    runs = {"bf16": {"step_s": 2e-3, "step": lambda: advance(2e-3, 600.0)},
+            "f32": {"step_s": 3e-3, "step": lambda: advance(3e-3, 500.0)}}
+    out = bench.energy_leg(fake_torch(), meter, runs, 1e9, seconds=2.0, preroll=3.0, reps=3)
+    assert out["idle_W"] == pytest.approx(100.0, rel=1e-3)
+    for name, w in (("bf16", 600.0), ("f32", 500.0)):
+        each = out[name]["J_per_1e12_bt_each"]
+        assert max(each) == pytest.approx(min(each), rel=1e-3), each
+        assert out[name]["avg_W"] == pytest.approx(w, rel=1e-3)
+    # J per 1e12 bt = W x step time / bt x 1e12
+    assert out["bf16"]["J_per_1e12_bt"] == pytest.approx(600.0 * 2e-3 / 1e9 * 1e12, rel=1e-3)
