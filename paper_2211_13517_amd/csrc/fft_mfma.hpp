@@ -24,8 +24,8 @@
 // FP16 (v_pk_mul_f16, v_pk_fma_f16, FP16 table); the last twiddles and the
 // radix-4 stage are FP32 vector arithmetic.
 //
-// Input: lane l (= 16 q + n) holds x[64 c + l] in h[c] (an FP16 pair).  Output: y[e][kb] of
-// lane (q, n) is y[n + 64 q + 16 e + 256 kb].
+// Input: lane l (= 16 q + n) holds x[64 c + l] in h[c] (an FP16 pair).
+// Output: y[e][kb] of lane (q, n) is y[n + 64 q + 16 e + 256 kb].
 #pragma once
 #include "common.hpp"
 
@@ -48,7 +48,8 @@ __device__ __forceinline__ uint32_t pack_h2(float a, float b) {
 }
 
 // Per-lane DFT-16 weights: w0 (real outputs) and w1 (imaginary outputs) for
-// lane (q, n), element e: index idx = q + 4 (e/2), part e%2, w = w16^{idx n}.
+// lane (q, n), element e: index idx = q + 4 (e/2), part e%2, w = w16^{idx n}
+// (FP64 phases, rounded to FP32 and then to FP16).
 struct Weights {
   h8 w0, w1;
 };
@@ -67,7 +68,8 @@ __device__ __forceinline__ Weights make_weights(int lane) {
   return W;
 }
 
-// Twiddle tables (FP64 phases, rounded once), filled by the block:
+// Twiddle tables (FP64 phases rounded to FP32, and for tw2 then to FP16),
+// filled by the block:
 //   tw2[l * kTw2Stride + 4 j + t] = w^{n (16 t + 4 q + j)}  for lane l = 16 q + n (FP16 pairs)
 //   tw3[12 q + 4 (j - 1) + e]     = w64^{j (4 q + e)}       for j = 1..3 (FP32)
 __device__ __forceinline__ void fill_tables(uint32_t* tw2, c32* tw3, int tid, int nthreads) {
@@ -141,10 +143,10 @@ __device__ __forceinline__ void ifft1024(uint32_t (&h)[16], c32 (&y)[4][4], cons
   for (int j = 0; j < 4; ++j) {
     const uint4 tj = twl[j];
     const uint32_t tt[4] = {tj.x, tj.y, tj.z, tj.w};
-    uint4 b;
-    uint32_t* bb = &b.x;
+    uint32_t bb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) bb[t] = cmul_h2(pack_h2(d0[t][j], d1[t][j]), tt[t]);
+    const uint4 b = {bb[0], bb[1], bb[2], bb[3]};
     const h8 B = __builtin_bit_cast(h8, b);
     const f4 z = {0.f, 0.f, 0.f, 0.f};
     const f4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(W.w0, B, z, 0, 0, 0);
