@@ -193,8 +193,11 @@ fdas_status fdas_spectrum(fdas_plan_t plan, const float *series, const int64_t *
  * matrix-core products with FP32 sums, the products with the templates are
  * FP16 (templates rounded once from FP64 to FP16, times 2^10), and every
  * segment's operands are scaled by a power of two that keeps them inside
- * FP16's range (undone exactly on the power); the error this adds to an
- * output is about 2^-11 of the segment's rms amplitude.
+ * FP16's range (undone exactly on the power; the scale covers segments whose
+ * largest spectrum component lies between about 2^-44 and 2^56 in
+ * magnitude, normalised spectra being of order 1, and a segment below that
+ * range yields powers of 0); the error this adds to an output is about
+ * 2^-11 of the segment's rms amplitude.
  * From a normalised spectrum (store_dtype, packed): overlap-save
  * segments of L bins starting at s U - h' (zero outside [0, N/2); h' and U
  * as at fdas_plan), one forward FFT per segment, then for every template j:
